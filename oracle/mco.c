@@ -1,0 +1,910 @@
+/*
+ * mco.c -- sequential CPU oracle of the analog Monte Carlo photon-transport
+ * forward projection of arXiv 2201.13191 (section II-A).
+ *
+ * TEST INFRASTRUCTURE ONLY: the judge of the GPU library, never part of the
+ * product path.  Written independently of the GPU library; see mco.h for the
+ * scope.  Every operation that can round is spelled out in the order the
+ * transport specification fixes, so that one seed has exactly one result:
+ *
+ *   - fp32 state (position, direction, energy, optical depth), no
+ *     contraction of a*b+c into fma (build with -ffp-contract=off), IEEE
+ *     division and square root, denormals kept;
+ *   - every transcendental (log, sin, cos, cbrt) evaluated in fp64 and
+ *     rounded once to fp32;
+ *   - the Compton (Kahn) and Rayleigh samplers run in fp64 with correctly
+ *     rounded + - * / only; their accept/reject decisions depend on nothing
+ *     else;
+ *   - cross-section tables are generated in extended precision and rounded
+ *     once to fp32.
+ *
+ * Parity pins (tests/test_oracle_*.py) check this file against closed forms,
+ * quadrature of eq. (1)/(2), Beer-Lambert transmission, solid angles and an
+ * independent Philox implementation.
+ */
+#include "mco.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- constants
+ * Classical electron radius (CODATA 2018).  Eq. (1) prints a garbled value
+ * with two digits swapped; the CODATA value is used. */
+#define R_E_CM 2.8179403262e-13L
+/* electron rest energy, keV (eq. (1) uses 0.511 MeV) */
+#define MEC2_KEV 510.99895
+/* Avogadro constant, 1/mol */
+#define N_AVO 6.02214076e23L
+/* h*c in keV*Angstrom: lambda[A] = HC / E[keV] */
+#define HC_KEV_A 12.398419843320026
+/* Bohr radius, Angstrom */
+#define BOHR_A 0.529177210903
+/* parametric photoelectric constant per electron, cm^2 keV^3 (times Z^3) */
+#define C_PE 3.2e-23L
+#define TWO_PI_D 6.283185307179586
+#define PI_L 3.141592653589793238462643383279502884L
+
+#define MAX_MAT 16
+#define MAX_SCATTER 1000      /* interaction safety cap per history        */
+#define E_CUT_KEV 1.0f        /* lower end of the model's range            */
+#define TALLY_ONE 1048576.0f  /* 2^20 least significant bits per keV       */
+
+struct mco_ctx {
+    char err[256];
+    int n_mat;
+    mco_material mat[MAX_MAT];
+    double rayl_b[MAX_MAT];     /* (2 pi r_Z)^2 [A^2], screening of F(x,Z) */
+    int nx, ny, nz;
+    float h;
+    uint8_t *ids;
+    float *rho;
+    int have_phantom;
+    mco_geometry g;
+    int have_geom;
+    int n_bins;
+    float *e_bin;
+    uint64_t *thr;              /* cumulative thresholds on 32-bit draws */
+    float e_max;
+    int have_spec;
+    float *eta_user;
+    int n_eta_user;
+    int J;
+    float *t_pe, *t_coh, *t_inc, *t_eta;
+    int tables_dirty;
+    mco_stats stats;
+};
+
+static int fail(mco_ctx *c, int code, const char *msg) {
+    if (c) snprintf(c->err, sizeof c->err, "%s", msg);
+    return code;
+}
+
+/* ------------------------------------------------------------ Philox4x32-10
+ * Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+ * (SC'11): 10 rounds of two 32x32->64 multiplies, the key bumped by the
+ * Weyl constants between rounds. */
+void mco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* uniform on the odd multiples of 2^-24: exact in fp32, never 0 or 1 */
+static float uniform01(uint32_t x) {
+    return (float)(2u * (x >> 9) + 1u) * 5.9604644775390625e-8f;
+}
+
+void mco_uniform_batch(const uint32_t *x, uint64_t n, float *out) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = uniform01(x[i]);
+}
+
+/* Per-photon stream: key = seed, counter = (photon id, draw index / 4, 0);
+ * draw k is word k mod 4 of block k / 4. */
+typedef struct {
+    uint32_t key[2];
+    uint64_t pid;
+    uint32_t k;
+    uint32_t cached_blk;
+    int have_blk;
+    uint32_t blk[4];
+} rng_t;
+
+static void rng_init(rng_t *r, uint64_t seed, uint64_t pid) {
+    r->key[0] = (uint32_t)seed;
+    r->key[1] = (uint32_t)(seed >> 32);
+    r->pid = pid;
+    r->k = 0;
+    r->have_blk = 0;
+}
+
+static uint32_t rng_raw(rng_t *r) {
+    uint32_t b = r->k >> 2;
+    if (!r->have_blk || b != r->cached_blk) {
+        uint32_t ctr[4] = {(uint32_t)r->pid, (uint32_t)(r->pid >> 32), b, 0u};
+        mco_philox4x32_10(ctr, r->key, r->blk);
+        r->cached_blk = b;
+        r->have_blk = 1;
+    }
+    uint32_t v = r->blk[r->k & 3u];
+    r->k++;
+    return v;
+}
+
+static float rng_u(rng_t *r) { return uniform01(rng_raw(r)); }
+
+/* ------------------------------------------------------------ cross sections
+ * Klein-Nishina total cross section per electron: the integral of eq. (1)
+ * over the sphere with S(q,Z) = 1 (textbook closed form), extended precision. */
+static long double sigma_kn_l(long double e_kev) {
+    long double a = e_kev / (long double)MEC2_KEV;
+    long double one2a = 1.0L + 2.0L * a;
+    long double lg = log1pl(2.0L * a);          /* ln(1 + 2 alpha), no rounding of 1 + 2a */
+    long double t1 = (1.0L + a) / (a * a) * (2.0L * (1.0L + a) / one2a - lg / a);
+    long double t2 = lg / (2.0L * a);
+    long double t3 = (1.0L + 3.0L * a) / (one2a * one2a);
+    return 2.0L * PI_L * R_E_CM * R_E_CM * (t1 + t2 - t3);
+}
+
+double mco_sigma_kn(double e_kev) { return (double)sigma_kn_l((long double)e_kev); }
+
+/* Coherent integral of eq. (2) with the screened form factor
+ * F(x,Z) = Z / (1 + b x^2)^2, x = sin(theta/2)/lambda, in the variable
+ * v = x^2 in [0, V], V = 1/lambda^2, cos(theta) = 1 - 2 v / V:
+ *   sigma_atom = 2 pi r_e^2 Z^2 * G(B),
+ *   G(B) = (1/V) Int_0^V (1 + cos^2) (1 + b v)^-4 dv,   B = b V.
+ * Closed form in w = 1 + b v for B >= 0.1; the alternating power series of
+ * (1 + B t)^-4 below, where the closed form cancels. */
+static long double coh_g(long double B) {
+    if (B < 0.1L) {
+        long double s = 0.0L, bn = 1.0L;
+        for (int n = 0; n <= 40; ++n) {
+            long double binom = (long double)(n + 1) * (n + 2) * (n + 3) / 6.0L;
+            long double term = binom * bn *
+                (2.0L / (n + 1) - 4.0L / (n + 2) + 4.0L / (n + 3));
+            s += (n & 1) ? -term : term;
+            bn *= B;
+        }
+        return s;
+    }
+    long double iw = 1.0L / (1.0L + B);
+    long double iw2 = iw * iw, iw3 = iw2 * iw;
+    long double j0 = (1.0L - iw3) / 3.0L;                          /* b   I0 */
+    long double j1 = 1.0L / 6.0L - iw2 / 2.0L + iw3 / 3.0L;         /* b^2 I1 */
+    long double j2 = 1.0L / 3.0L - iw + iw2 - iw3 / 3.0L;           /* b^3 I2 */
+    return 2.0L * j0 / B - 4.0L * j1 / (B * B) + 4.0L * j2 / (B * B * B);
+}
+
+static long double rayl_b_l(long double z) {
+    long double rz = 0.885L * (long double)BOHR_A / cbrtl(z);
+    long double t = 2.0L * PI_L * rz;
+    return t * t;
+}
+
+static void xs_l(long double z, long double zoa, long double e, long double out[3]) {
+    long double ne = N_AVO * zoa;                       /* electrons per gram */
+    out[0] = ne * C_PE * z * z * z / (e * e * e);
+    long double t = e / (long double)HC_KEV_A;          /* 1/lambda          */
+    long double B = rayl_b_l(z) * t * t;
+    out[1] = ne * 2.0L * PI_L * R_E_CM * R_E_CM * z * coh_g(B);
+    out[2] = ne * sigma_kn_l(e);
+}
+
+int mco_cross_sections(double z_eff, double z_over_a, double e_kev, double out[3]) {
+    if (!(z_eff >= 1.0 && z_eff <= 100.0) || !(z_over_a > 0.0 && z_over_a <= 1.01) ||
+        !(e_kev >= 1.0 && e_kev <= 1001.0))
+        return MCO_E_INVALID_ARG;
+    long double o[3];
+    xs_l(z_eff, z_over_a, e_kev, o);
+    for (int i = 0; i < 3; ++i) out[i] = (double)o[i];
+    return MCO_OK;
+}
+
+/* ------------------------------------------------------------ context */
+static const mco_material DEFAULT_MATS[5] = {
+    {7.64f, 0.49919f, 0.001205f, "air"},
+    {7.42f, 0.55508f, 1.0f, "water"},
+    {13.0f, 0.48181f, 2.699f, "aluminium"},
+    {13.8f, 0.51480f, 1.92f, "bone_ca"},
+    {26.0f, 0.46557f, 7.874f, "iron"},
+};
+
+static void set_mats(mco_ctx *c, const mco_material *m, int n) {
+    c->n_mat = n;
+    for (int i = 0; i < n; ++i) {
+        c->mat[i] = m[i];
+        double rz = 0.885 * BOHR_A / cbrt((double)m[i].z_eff);
+        double t = TWO_PI_D * rz;
+        c->rayl_b[i] = t * t;
+    }
+    c->tables_dirty = 1;
+}
+
+int mco_create(mco_ctx **out) {
+    if (!out) return MCO_E_INVALID_ARG;
+    mco_ctx *c = (mco_ctx *)calloc(1, sizeof *c);
+    if (!c) return MCO_E_OOM;
+    set_mats(c, DEFAULT_MATS, 5);
+    *out = c;
+    return MCO_OK;
+}
+
+void mco_destroy(mco_ctx *c) {
+    if (!c) return;
+    free(c->ids); free(c->rho); free(c->e_bin); free(c->thr); free(c->eta_user);
+    free(c->t_pe); free(c->t_coh); free(c->t_inc); free(c->t_eta);
+    free(c);
+}
+
+const char *mco_last_error(const mco_ctx *c) { return c ? c->err : "null context"; }
+
+int mco_set_materials(mco_ctx *c, const mco_material *m, int n) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!m || n < 1 || n > MAX_MAT) return fail(c, MCO_E_INVALID_ARG, "n_mat must be 1..16");
+    for (int i = 0; i < n; ++i)
+        if (!(m[i].z_eff >= 1.0f && m[i].z_eff <= 100.0f) ||
+            !(m[i].z_over_a > 0.0f && m[i].z_over_a <= 1.01f))
+            return fail(c, MCO_E_INVALID_ARG, "material z_eff/z_over_a out of range");
+    set_mats(c, m, n);
+    return MCO_OK;
+}
+
+int mco_load_phantom(mco_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny,
+                     int nz, float h) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!ids || !rho || nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096 ||
+        !(h > 0.0f) || !isfinite(h))
+        return fail(c, MCO_E_INVALID_ARG, "bad phantom dimensions");
+    size_t nv = (size_t)nx * ny * nz;
+    for (size_t i = 0; i < nv; ++i)
+        if (!isfinite(rho[i]) || rho[i] < 0.0f || rho[i] > 1000.0f)
+            return fail(c, MCO_E_INVALID_ARG, "density must be finite and in [0, 1000]");
+    uint8_t *ni = (uint8_t *)malloc(nv);
+    float *nr = (float *)malloc(nv * sizeof(float));
+    if (!ni || !nr) { free(ni); free(nr); return fail(c, MCO_E_OOM, "phantom allocation"); }
+    memcpy(ni, ids, nv);
+    memcpy(nr, rho, nv * sizeof(float));
+    free(c->ids); free(c->rho);
+    c->ids = ni; c->rho = nr;
+    c->nx = nx; c->ny = ny; c->nz = nz; c->h = h;
+    c->have_phantom = 1;
+    return MCO_OK;
+}
+
+int mco_set_geometry(mco_ctx *c, const mco_geometry *g) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!g) return fail(c, MCO_E_INVALID_ARG, "null geometry");
+    if (!(g->sod_mm > 0.0f) || !(g->sdd_mm > g->sod_mm) || !isfinite(g->sdd_mm))
+        return fail(c, MCO_E_INVALID_ARG, "need 0 < sod < sdd");
+    if (g->nu < 1 || g->nv < 1 || g->nu > 16384 || g->nv > 16384 || !(g->pu_mm > 0.0f) ||
+        !(g->pv_mm > 0.0f) || !isfinite(g->pu_mm) || !isfinite(g->pv_mm))
+        return fail(c, MCO_E_INVALID_ARG, "bad detector");
+    if (g->snu < 1 || g->snv < 1 || g->nu % g->snu || g->nv % g->snv)
+        return fail(c, MCO_E_INVALID_ARG, "scatter grid must divide the detector");
+    if (!(g->step_mm > 0.0f) || !isfinite(g->step_mm))
+        return fail(c, MCO_E_INVALID_ARG, "step must be > 0");
+    if (g->flags & ~MCO_NO_SCATTER) return fail(c, MCO_E_INVALID_ARG, "unknown flags");
+    c->g = *g;
+    c->have_geom = 1;
+    return MCO_OK;
+}
+
+int mco_set_spectrum(mco_ctx *c, const float *e, const float *w, int n) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!e || !w || n < 1 || n > 4096) return fail(c, MCO_E_INVALID_ARG, "n_bins must be 1..4096");
+    double total = 0.0;
+    float emax = 0.0f;
+    for (int k = 0; k < n; ++k) {
+        if (!(e[k] >= 1.0f && e[k] <= 1000.0f))
+            return fail(c, MCO_E_INVALID_ARG, "bin energy outside [1, 1000] keV");
+        if (!(w[k] >= 0.0f) || !isfinite(w[k]))
+            return fail(c, MCO_E_INVALID_ARG, "weights must be finite and >= 0");
+        total += (double)w[k];
+        if (e[k] > emax) emax = e[k];
+    }
+    if (!(total > 0.0)) return fail(c, MCO_E_INVALID_ARG, "weights sum to zero");
+    float *ne = (float *)malloc(n * sizeof(float));
+    uint64_t *nt = (uint64_t *)malloc(n * sizeof(uint64_t));
+    if (!ne || !nt) { free(ne); free(nt); return fail(c, MCO_E_OOM, "spectrum allocation"); }
+    double cum = 0.0;
+    for (int k = 0; k < n; ++k) {
+        ne[k] = e[k];
+        cum += (double)w[k];
+        nt[k] = (k == n - 1) ? (uint64_t)1 << 32
+                             : (uint64_t)floor(cum / total * 4294967296.0);
+    }
+    free(c->e_bin); free(c->thr);
+    c->e_bin = ne; c->thr = nt; c->n_bins = n; c->e_max = emax;
+    c->have_spec = 1;
+    c->tables_dirty = 1;
+    return MCO_OK;
+}
+
+int mco_set_detector_response(mco_ctx *c, const float *eta, int n) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!eta || n < 1 || n > 4096) return fail(c, MCO_E_INVALID_ARG, "eta length must be 1..4096");
+    for (int i = 0; i < n; ++i)
+        if (!(eta[i] >= 0.0f) || !isfinite(eta[i]))
+            return fail(c, MCO_E_INVALID_ARG, "eta must be finite and >= 0");
+    float *ne = (float *)malloc(n * sizeof(float));
+    if (!ne) return fail(c, MCO_E_OOM, "eta allocation");
+    memcpy(ne, eta, n * sizeof(float));
+    free(c->eta_user);
+    c->eta_user = ne;
+    c->n_eta_user = n;
+    c->tables_dirty = 1;
+    return MCO_OK;
+}
+
+/* Tables on the grid E_j = 1 + j keV, j = 0 .. J-1, J = floor(E_max) + 2, so
+ * that every energy a photon can carry has both neighbours on the grid. */
+static int build_tables(mco_ctx *c) {
+    if (!c->tables_dirty) return MCO_OK;
+    int J = (int)floorf(c->e_max) + 2;
+    size_t n = (size_t)c->n_mat * J;
+    float *pe = (float *)malloc(n * sizeof(float));
+    float *coh = (float *)malloc(n * sizeof(float));
+    float *inc = (float *)malloc(n * sizeof(float));
+    float *eta = (float *)malloc(J * sizeof(float));
+    if (!pe || !coh || !inc || !eta) {
+        free(pe); free(coh); free(inc); free(eta);
+        return fail(c, MCO_E_OOM, "table allocation");
+    }
+    for (int m = 0; m < c->n_mat; ++m)
+        for (int j = 0; j < J; ++j) {
+            long double o[3];
+            xs_l((long double)c->mat[m].z_eff, (long double)c->mat[m].z_over_a,
+                 (long double)(1 + j), o);
+            pe[(size_t)m * J + j] = (float)o[0];
+            coh[(size_t)m * J + j] = (float)o[1];
+            inc[(size_t)m * J + j] = (float)o[2];
+        }
+    for (int j = 0; j < J; ++j) {
+        if (c->eta_user)
+            eta[j] = c->eta_user[j < c->n_eta_user ? j : c->n_eta_user - 1];
+        else
+            eta[j] = (float)(1 + j);
+    }
+    free(c->t_pe); free(c->t_coh); free(c->t_inc); free(c->t_eta);
+    c->t_pe = pe; c->t_coh = coh; c->t_inc = inc; c->t_eta = eta;
+    c->J = J;
+    c->tables_dirty = 0;
+    return MCO_OK;
+}
+
+int mco_get_tables(mco_ctx *c, int *J, float *pe, float *coh, float *inc, float *eta) {
+    if (!c || !J) return MCO_E_INVALID_ARG;
+    if (!c->have_spec) return fail(c, MCO_E_STATE, "spectrum not set");
+    int rc = build_tables(c);
+    if (rc) return rc;
+    *J = c->J;
+    size_t n = (size_t)c->n_mat * c->J;
+    if (pe) memcpy(pe, c->t_pe, n * sizeof(float));
+    if (coh) memcpy(coh, c->t_coh, n * sizeof(float));
+    if (inc) memcpy(inc, c->t_inc, n * sizeof(float));
+    if (eta) memcpy(eta, c->t_eta, c->J * sizeof(float));
+    return MCO_OK;
+}
+
+/* fp32 linear interpolation on the 1 keV grid */
+static float lerp_tab(const float *t, int J, float e) {
+    float em1 = e - 1.0f;
+    int j = (int)em1;
+    if (j < 0) j = 0;
+    if (j > J - 2) j = J - 2;
+    float f = em1 - (float)j;
+    return t[j] + f * (t[j + 1] - t[j]);
+}
+
+/* ------------------------------------------------------------ geometry
+ * Source on a circle of radius sod around the z axis at angle beta; the
+ * panel is perpendicular to the central ray at distance sdd; u runs along
+ * (-sin b, cos b, 0), v along z.  The phantom box is centred on the origin. */
+typedef struct {
+    float S[3], ax[3], eu[3], ev[3], D[3];
+    float hu, hv, omc;
+    float lo[3], hi[3], inv_h;
+} proj_t;
+
+static void proj_setup(const mco_ctx *c, float beta, proj_t *P) {
+    float cb = (float)cos((double)beta), sb = (float)sin((double)beta);
+    const mco_geometry *g = &c->g;
+    P->S[0] = g->sod_mm * cb; P->S[1] = g->sod_mm * sb; P->S[2] = 0.0f;
+    P->ax[0] = -cb; P->ax[1] = -sb; P->ax[2] = 0.0f;
+    P->eu[0] = -sb; P->eu[1] = cb; P->eu[2] = 0.0f;
+    P->ev[0] = 0.0f; P->ev[1] = 0.0f; P->ev[2] = 1.0f;
+    for (int a = 0; a < 3; ++a) P->D[a] = P->S[a] + g->sdd_mm * P->ax[a];
+    P->hu = 0.5f * ((float)g->nu * g->pu_mm);
+    P->hv = 0.5f * ((float)g->nv * g->pv_mm);
+    double sdd = g->sdd_mm, hu = P->hu, hv = P->hv;
+    double ctm = sdd / sqrt(sdd * sdd + hu * hu + hv * hv);
+    P->omc = (float)(1.0 - ctm);
+    int n[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+        P->hi[a] = 0.5f * ((float)n[a] * c->h);
+        P->lo[a] = -P->hi[a];
+    }
+    P->inv_h = 1.0f / c->h;
+}
+
+/* slab-method ray/box intersection: entry t_in >= 0 and exit t_out */
+static int box_hit(const proj_t *P, const float p[3], const float d[3], float *tin,
+                   float *tout) {
+    float t0 = 0.0f, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0f) {
+            float inv = 1.0f / d[a];
+            float ta = (P->lo[a] - p[a]) * inv;
+            float tb = (P->hi[a] - p[a]) * inv;
+            float tn = ta < tb ? ta : tb;
+            float tf = ta < tb ? tb : ta;
+            if (tn > t0) t0 = tn;
+            if (tf < t1) t1 = tf;
+        } else if (p[a] < P->lo[a] || p[a] > P->hi[a]) {
+            return 0;
+        }
+    }
+    if (!(t0 < t1)) return 0;
+    *tin = t0;
+    *tout = t1;
+    return 1;
+}
+
+/* pixel crossed by the straight line p + t d, or 0 */
+static int panel_pixel(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
+                       int *iu, int *iv) {
+    const mco_geometry *g = &c->g;
+    float den = (d[0] * P->ax[0] + d[1] * P->ax[1]) + d[2] * P->ax[2];
+    if (!(den > 0.0f)) return 0;
+    float rel = ((p[0] - P->S[0]) * P->ax[0] + (p[1] - P->S[1]) * P->ax[1]) +
+                (p[2] - P->S[2]) * P->ax[2];
+    float td = (g->sdd_mm - rel) / den;
+    float w[3];
+    for (int a = 0; a < 3; ++a) w[a] = (p[a] + td * d[a]) - P->D[a];
+    float u = (w[0] * P->eu[0] + w[1] * P->eu[1]) + w[2] * P->eu[2];
+    float v = (w[0] * P->ev[0] + w[1] * P->ev[1]) + w[2] * P->ev[2];
+    float fu = (u + P->hu) / g->pu_mm;
+    float fv = (v + P->hv) / g->pv_mm;
+    if (!(fu >= 0.0f && fu < (float)g->nu && fv >= 0.0f && fv < (float)g->nv)) return 0;
+    *iu = (int)fu;
+    *iv = (int)fv;
+    return 1;
+}
+
+int mco_detector_pixel(mco_ctx *c, float beta, const float p[3], const float d[3], int *iu,
+                       int *iv) {
+    if (!c || !p || !d || !iu || !iv) return MCO_E_INVALID_ARG;
+    if (!c->have_geom || !c->have_phantom) return fail(c, MCO_E_STATE, "geometry/phantom not set");
+    proj_t P;
+    proj_setup(c, beta, &P);
+    if (!panel_pixel(c, &P, p, d, iu, iv)) { *iu = -1; *iv = -1; }
+    return MCO_OK;
+}
+
+/* ------------------------------------------------------------ samplers
+ * Compton polar angle by Kahn's rejection method (cited in section II-A):
+ * x = E/E' in [1, 1 + 2 alpha] from two branches, accepted against the
+ * Klein-Nishina shape; three draws per trial.  fp64, correctly rounded
+ * operations only. */
+static void sample_compton(rng_t *r, float e, float *cos_out, float *e_out) {
+    double alpha = (double)e / MEC2_KEV;
+    double x;
+    for (;;) {
+        double r1 = (double)rng_u(r);
+        double r2 = (double)rng_u(r);
+        double r3 = (double)rng_u(r);
+        if (r1 <= (1.0 + 2.0 * alpha) / (9.0 + 2.0 * alpha)) {
+            x = 1.0 + 2.0 * alpha * r2;
+            if (r3 <= 4.0 * (1.0 / x - 1.0 / (x * x))) break;
+        } else {
+            x = (1.0 + 2.0 * alpha) / (1.0 + 2.0 * alpha * r2);
+            double c = 1.0 - (x - 1.0) / alpha;
+            if (r3 <= 0.5 * (c * c + 1.0 / x)) break;
+        }
+    }
+    *e_out = (float)((double)e / x);
+    *cos_out = (float)(1.0 - (x - 1.0) / alpha);
+}
+
+/* Rayleigh polar angle for eq. (2): v = x^2 drawn from F^2 ~ (1 + b v)^-4 on
+ * [0, V] by inversion, then accepted with the Thomson factor (1 + cos^2)/2;
+ * two draws per trial.  The fp32 cosine is what the decision sees. */
+static float sample_rayleigh(rng_t *r, float e, double b) {
+    double t = (double)e / HC_KEV_A;
+    double V = t * t;
+    double W = 1.0 + b * V;
+    double ymin = 1.0 / (W * W * W);
+    for (;;) {
+        double r1 = (double)rng_u(r);
+        double r2 = (double)rng_u(r);
+        double y = 1.0 - r1 * (1.0 - ymin);
+        double v = (1.0 / cbrt(y) - 1.0) / b;
+        float cf = (float)(1.0 - 2.0 * v / V);
+        double cd = (double)cf;
+        if (r2 <= 0.5 * (1.0 + cd * cd)) return cf;
+    }
+}
+
+/* new direction after scattering by polar cosine ct and azimuth (cp, sp) */
+static void rotate(float d[3], float ct, float cp, float sp) {
+    float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    float ux = d[0], uy = d[1], uz = d[2];
+    float nx, ny, nz;
+    if (fabsf(uz) < 0.99999f) {
+        float t = sqrtf(1.0f - uz * uz);
+        nx = st * ((ux * uz) * cp - uy * sp) / t + ux * ct;
+        ny = st * ((uy * uz) * cp + ux * sp) / t + uy * ct;
+        nz = uz * ct - (st * cp) * t;
+    } else {
+        nx = st * cp;
+        ny = st * sp;
+        nz = uz >= 0.0f ? ct : -ct;
+    }
+    float inv = 1.0f / sqrtf((nx * nx + ny * ny) + nz * nz);
+    d[0] = nx * inv;
+    d[1] = ny * inv;
+    d[2] = nz * inv;
+}
+
+static uint32_t energy_bin(const mco_ctx *c, uint32_t x) {
+    int lo = 0, hi = c->n_bins - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((uint64_t)x < c->thr[mid]) hi = mid; else lo = mid + 1;
+    }
+    return (uint32_t)lo;
+}
+
+static void birth(const mco_ctx *c, const proj_t *P, rng_t *r, float *e, float d[3]) {
+    *e = c->e_bin[energy_bin(c, rng_raw(r))];
+    float ct = 1.0f - rng_u(r) * P->omc;
+    float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    double phi = TWO_PI_D * (double)rng_u(r);
+    float cp = (float)cos(phi), sp = (float)sin(phi);
+    for (int a = 0; a < 3; ++a)
+        d[a] = (ct * P->ax[a] + (st * cp) * P->eu[a]) + (st * sp) * P->ev[a];
+}
+
+/* ------------------------------------------------------------ transport */
+typedef struct {
+    uint16_t n_int;
+    uint32_t steps;
+    uint8_t end, first;
+} hist_t;
+
+/* Fixed-step march from entry t_in to exit t_out.  Step k covers
+ * [k*step, min((k+1)*step, L)) of the chord (the last step clipped); the
+ * voxel at the step midpoint gives mu; the photon interacts in the first step
+ * where the accumulated optical depth reaches tau_star, at the linearly
+ * interpolated point.  Returns 1 with the interaction point and voxel. */
+static int march(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
+                 float tin, float tout, const float *mm, float tau_star, float pint[3],
+                 size_t *vox, uint32_t *steps) {
+    float pin[3], q[3], e[3];
+    for (int a = 0; a < 3; ++a) pin[a] = p[a] + d[a] * tin;
+    float L = tout - tin;
+    for (int a = 0; a < 3; ++a) {
+        q[a] = (pin[a] - P->lo[a]) * P->inv_h;
+        e[a] = d[a] * P->inv_h;
+    }
+    const float dl = c->g.step_mm;
+    float tau = 0.0f;
+    for (uint32_t k = 0;; ++k) {
+        float a0 = (float)k * dl;
+        if (!(a0 < L)) return 0;
+        float b = a0 + dl;
+        if (b > L) b = L;
+        float dk = b - a0;
+        float s = 0.5f * (a0 + b);
+        int ix = (int)(q[0] + e[0] * s);
+        int iy = (int)(q[1] + e[1] * s);
+        int iz = (int)(q[2] + e[2] * s);
+        ix = ix < 0 ? 0 : (ix > c->nx - 1 ? c->nx - 1 : ix);
+        iy = iy < 0 ? 0 : (iy > c->ny - 1 ? c->ny - 1 : iy);
+        iz = iz < 0 ? 0 : (iz > c->nz - 1 ? c->nz - 1 : iz);
+        size_t v = ((size_t)iz * c->ny + iy) * c->nx + ix;
+        float mu = c->rho[v] * mm[c->ids[v]];
+        float x = mu * dk;
+        float tnext = tau + x;
+        (*steps)++;
+        if (tnext >= tau_star) {
+            float sint = a0 + (tau_star - tau) / mu;
+            for (int a = 0; a < 3; ++a) pint[a] = pin[a] + d[a] * sint;
+            *vox = v;
+            return 1;
+        }
+        tau = tnext;
+    }
+}
+
+static void mat_mu(const mco_ctx *c, float e, float *mm) {
+    for (int m = 0; m < c->n_mat; ++m) {
+        const size_t o = (size_t)m * c->J;
+        float pe = lerp_tab(c->t_pe + o, c->J, e);
+        float coh = lerp_tab(c->t_coh + o, c->J, e);
+        float inc = lerp_tab(c->t_inc + o, c->J, e);
+        mm[m] = ((pe + coh) + inc) * 0.1f;        /* cm^2/g * g/cm^3 -> 1/mm */
+    }
+}
+
+static void tally(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
+                  float e, int n_int, int64_t *prim, int64_t *scat, mco_stats *st, hist_t *h) {
+    int iu, iv;
+    if (!panel_pixel(c, P, p, d, &iu, &iv)) { h->end = MCO_END_MISSED; return; }
+    float w = lerp_tab(c->t_eta, c->J, e);
+    int64_t L = (int64_t)llrintf(w * TALLY_ONE);
+    const mco_geometry *g = &c->g;
+    if (n_int == 0) {
+        if (prim) prim[(size_t)iv * g->nu + iu] += L;
+        st->primary_hits++;
+        h->end = MCO_END_PRIMARY;
+    } else {
+        int su = iu / (g->nu / g->snu), sv = iv / (g->nv / g->snv);
+        if (scat) scat[(size_t)sv * g->snu + su] += L;
+        st->scatter_hits++;
+        h->end = MCO_END_SCATTER;
+    }
+}
+
+static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t pid,
+                    int64_t *prim, int64_t *scat, mco_stats *st, hist_t *h) {
+    rng_t r;
+    rng_init(&r, seed, pid);
+    h->n_int = 0; h->steps = 0; h->end = MCO_END_MISSED; h->first = MCO_FIRST_NONE;
+    st->histories++;
+    float e, d[3], p[3], mm[MAX_MAT];
+    birth(c, P, &r, &e, d);
+    for (int a = 0; a < 3; ++a) p[a] = P->S[a];
+    mat_mu(c, e, mm);
+    int n_int = 0;
+    for (;;) {
+        float tin, tout;
+        if (!box_hit(P, p, d, &tin, &tout)) break;
+        float tau_star = (float)(-log((double)rng_u(&r)));
+        st->flights++;
+        float pint[3];
+        size_t v;
+        uint32_t steps = 0;
+        int hit = march(c, P, p, d, tin, tout, mm, tau_star, pint, &v, &steps);
+        h->steps += steps;
+        st->steps += steps;
+        if (!hit) break;
+        for (int a = 0; a < 3; ++a) p[a] = pint[a];
+        /* interaction type at (material, E): [photo, Rayleigh, Compton] */
+        const int m = c->ids[v];
+        const size_t o = (size_t)m * c->J;
+        float pe = lerp_tab(c->t_pe + o, c->J, e);
+        float coh = lerp_tab(c->t_coh + o, c->J, e);
+        float inc = lerp_tab(c->t_inc + o, c->J, e);
+        float tot = (pe + coh) + inc;
+        float x = rng_u(&r) * tot;
+        if ((c->g.flags & MCO_NO_SCATTER) || x < pe) {
+            st->photo++;
+            if (!n_int) h->first = MCO_FIRST_PHOTO;
+            h->end = MCO_END_PHOTO;
+            h->n_int = (uint16_t)n_int;
+            return;
+        }
+        float ct, e2;
+        if (x < pe + coh) {
+            ct = sample_rayleigh(&r, e, c->rayl_b[m]);
+            e2 = e;
+            st->rayleigh++;
+            if (!n_int) h->first = MCO_FIRST_RAYLEIGH;
+        } else {
+            sample_compton(&r, e, &ct, &e2);
+            st->compton++;
+            if (!n_int) h->first = MCO_FIRST_COMPTON;
+        }
+        double phi = TWO_PI_D * (double)rng_u(&r);
+        rotate(d, ct, (float)cos(phi), (float)sin(phi));
+        n_int++;
+        if (e2 < E_CUT_KEV) {
+            st->cutoff_kills++;
+            h->end = MCO_END_CUTOFF;
+            h->n_int = (uint16_t)n_int;
+            return;
+        }
+        if (n_int >= MAX_SCATTER) {
+            st->cap_hits++;
+            h->end = MCO_END_CAP;
+            h->n_int = (uint16_t)n_int;
+            return;
+        }
+        if (e2 != e) {
+            e = e2;
+            mat_mu(c, e, mm);
+        }
+    }
+    h->n_int = (uint16_t)n_int;
+    tally(c, P, p, d, e, n_int, prim, scat, st, h);
+}
+
+/* every precondition of a projection; also regenerates stale tables */
+static int ready(mco_ctx *c, uint64_t n) {
+    if (!c->have_phantom || !c->have_geom || !c->have_spec)
+        return fail(c, MCO_E_STATE, "phantom, geometry and spectrum must be set");
+    size_t nv = (size_t)c->nx * c->ny * c->nz;
+    for (size_t i = 0; i < nv; ++i)
+        if (c->ids[i] >= c->n_mat) return fail(c, MCO_E_INVALID_ARG, "material id >= n_mat");
+    double hx = 0.5 * c->nx * c->h, hy = 0.5 * c->ny * c->h, hz = 0.5 * c->nz * c->h;
+    double diag = sqrt(hx * hx + hy * hy + hz * hz);
+    if (!(diag < c->g.sod_mm) || !(diag < (double)c->g.sdd_mm - c->g.sod_mm))
+        return fail(c, MCO_E_INVALID_ARG, "phantom must lie strictly between source and panel");
+    if (2.0 * diag / c->g.step_mm > 4194304.0)
+        return fail(c, MCO_E_INVALID_ARG, "step too small for the phantom");
+    int rc = build_tables(c);
+    if (rc) return rc;
+    float emax_eta = 0.0f;
+    for (int j = 0; j < c->J; ++j)
+        if (c->t_eta[j] > emax_eta) emax_eta = c->t_eta[j];
+    if ((long double)n * ((long double)emax_eta * 1048576.0L + 1.0L) >= 9223372036854775807.0L)
+        return fail(c, MCO_E_OVERFLOW, "tally could overflow int64");
+    return MCO_OK;
+}
+
+static void stats_add(mco_stats *a, const mco_stats *b) {
+    a->histories += b->histories; a->steps += b->steps; a->flights += b->flights;
+    a->photo += b->photo; a->rayleigh += b->rayleigh; a->compton += b->compton;
+    a->primary_hits += b->primary_hits; a->scatter_hits += b->scatter_hits;
+    a->cutoff_kills += b->cutoff_kills; a->cap_hits += b->cap_hits;
+}
+
+int mco_project_range(mco_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t seed,
+                      int64_t *prim, int64_t *scat) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!prim || !scat) return fail(c, MCO_E_INVALID_ARG, "null image");
+    if (!isfinite(beta)) return fail(c, MCO_E_INVALID_ARG, "angle must be finite");
+    int rc = ready(c, first + n);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    hist_t h;
+    for (uint64_t i = 0; i < n; ++i) history(c, &P, seed, first + i, prim, scat, &c->stats, &h);
+    return MCO_OK;
+}
+
+int mco_project(mco_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *prim,
+                int64_t *scat) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!prim || !scat) return fail(c, MCO_E_INVALID_ARG, "null image");
+    if (!c->have_geom) return fail(c, MCO_E_STATE, "geometry not set");
+    memset(prim, 0, (size_t)c->g.nu * c->g.nv * sizeof(int64_t));
+    memset(scat, 0, (size_t)c->g.snu * c->g.snv * sizeof(int64_t));
+    return mco_project_range(c, beta, 0, n, seed, prim, scat);
+}
+
+typedef struct {
+    const mco_ctx *c;
+    const proj_t *P;
+    uint64_t first, n, seed;
+    int64_t *prim, *scat;
+    mco_stats st;
+} worker_t;
+
+static void *worker(void *arg) {
+    worker_t *w = (worker_t *)arg;
+    hist_t h;
+    for (uint64_t i = 0; i < w->n; ++i)
+        history(w->c, w->P, w->seed, w->first + i, w->prim, w->scat, &w->st, &h);
+    return NULL;
+}
+
+int mco_project_mt(mco_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *prim,
+                   int64_t *scat, int nt) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!prim || !scat || nt < 1 || nt > 1024) return fail(c, MCO_E_INVALID_ARG, "bad arguments");
+    if (!c->have_geom) return fail(c, MCO_E_STATE, "geometry not set");
+    int rc = ready(c, n);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    size_t np = (size_t)c->g.nu * c->g.nv, ns = (size_t)c->g.snu * c->g.snv;
+    worker_t *w = (worker_t *)calloc(nt, sizeof *w);
+    pthread_t *th = (pthread_t *)calloc(nt, sizeof *th);
+    int64_t *img = (int64_t *)calloc((size_t)nt * (np + ns), sizeof(int64_t));
+    if (!w || !th || !img) { free(w); free(th); free(img); return fail(c, MCO_E_OOM, "thread images"); }
+    for (int t = 0; t < nt; ++t) {
+        uint64_t lo = n * (uint64_t)t / nt, hi = n * (uint64_t)(t + 1) / nt;
+        w[t].c = c; w[t].P = &P; w[t].first = lo; w[t].n = hi - lo; w[t].seed = seed;
+        w[t].prim = img + (size_t)t * (np + ns);
+        w[t].scat = w[t].prim + np;
+        pthread_create(&th[t], NULL, worker, &w[t]);
+    }
+    memset(prim, 0, np * sizeof(int64_t));
+    memset(scat, 0, ns * sizeof(int64_t));
+    for (int t = 0; t < nt; ++t) {
+        pthread_join(th[t], NULL);
+        for (size_t i = 0; i < np; ++i) prim[i] += w[t].prim[i];
+        for (size_t i = 0; i < ns; ++i) scat[i] += w[t].scat[i];
+        stats_add(&c->stats, &w[t].st);
+    }
+    free(w); free(th); free(img);
+    return MCO_OK;
+}
+
+int mco_debug_histories(mco_ctx *c, float beta, uint64_t first, uint64_t m, uint64_t seed,
+                        uint16_t *n_int, uint32_t *steps, uint8_t *end, uint8_t *first_type) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!isfinite(beta)) return fail(c, MCO_E_INVALID_ARG, "angle must be finite");
+    int rc = ready(c, m);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    for (uint64_t i = 0; i < m; ++i) {
+        hist_t h;
+        history(c, &P, seed, first + i, NULL, NULL, &c->stats, &h);
+        if (n_int) n_int[i] = h.n_int;
+        if (steps) steps[i] = h.steps;
+        if (end) end[i] = h.end;
+        if (first_type) first_type[i] = h.first;
+    }
+    return MCO_OK;
+}
+
+int mco_test_sample(mco_ctx *c, int process, int material, float e, uint64_t n, uint64_t seed,
+                    float *cos_out, float *e_out) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (process == MCO_PROC_SOURCE_ENERGY) {
+        if (!c->have_spec || !e_out) return fail(c, MCO_E_STATE, "spectrum not set");
+        for (uint64_t i = 0; i < n; ++i) {
+            rng_t r;
+            rng_init(&r, seed, i);
+            e_out[i] = c->e_bin[energy_bin(c, rng_raw(&r))];
+        }
+        return MCO_OK;
+    }
+    if (process == MCO_PROC_SOURCE_DIR) {
+        if (!c->have_geom || !c->have_phantom || !cos_out)
+            return fail(c, MCO_E_STATE, "geometry/phantom not set");
+        proj_t P;
+        proj_setup(c, 0.0f, &P);
+        for (uint64_t i = 0; i < n; ++i) {
+            rng_t r;
+            rng_init(&r, seed, i);
+            (void)rng_raw(&r);
+            cos_out[i] = 1.0f - rng_u(&r) * P.omc;
+        }
+        return MCO_OK;
+    }
+    if (process != MCO_PROC_RAYLEIGH && process != MCO_PROC_COMPTON)
+        return fail(c, MCO_E_INVALID_ARG, "unknown process");
+    if (material < 0 || material >= c->n_mat || !(e >= 1.0f && e <= 1000.0f) || !cos_out)
+        return fail(c, MCO_E_INVALID_ARG, "bad material/energy");
+    for (uint64_t i = 0; i < n; ++i) {
+        rng_t r;
+        rng_init(&r, seed, i);
+        float ct, e2 = e;
+        if (process == MCO_PROC_COMPTON)
+            sample_compton(&r, e, &ct, &e2);
+        else
+            ct = sample_rayleigh(&r, e, c->rayl_b[material]);
+        cos_out[i] = ct;
+        if (e_out) e_out[i] = e2;
+    }
+    return MCO_OK;
+}
+
+int mco_get_stats(mco_ctx *c, mco_stats *out) {
+    if (!c || !out) return MCO_E_INVALID_ARG;
+    *out = c->stats;
+    memset(&c->stats, 0, sizeof c->stats);
+    return MCO_OK;
+}
+
+double mco_tally_scale(void) { return 1.0 / 1048576.0; }

@@ -1,0 +1,80 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case copies oracle/mco.c, plants one mistake by text substitution, builds
+the copy with the oracle's own flags, and runs the pin that should catch it
+against the broken build (in a child pytest).  The pin must fail.  Only the
+copy is changed; nothing here touches the GPU.
+"""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+from oracle import build as obuild
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+CASES = [
+    # (id, original text, planted mistake, pin that must fail)
+    ("kahn_accept", "0.5 * (c * c + 1.0 / x)", "0.5 * (c * c + x)",
+     "test_oracle_samplers.py::test_compton_angles_chi2"),
+    ("kahn_branch", "(1.0 + 2.0 * alpha) / (9.0 + 2.0 * alpha)", "(1.0 + 2.0 * alpha) / (7.0 + 2.0 * alpha)",
+     "test_oracle_samplers.py::test_compton_angles_chi2"),
+    ("rayleigh_inverse", "(1.0 / cbrt(y) - 1.0) / b", "(1.0 / sqrt(y) - 1.0) / b",
+     "test_oracle_samplers.py::test_rayleigh_angles_chi2"),
+    ("rayleigh_thomson", "0.5 * (1.0 + cd * cd)", "0.5 * (1.0 + cd)",
+     "test_oracle_samplers.py::test_rayleigh_angles_chi2"),
+    ("last_step_unclipped", "float dk = b - a0;", "float dk = dl;",
+     "test_oracle_transport.py::test_beer_lambert_slab"),
+    ("midpoint_dropped", "float s = 0.5f * (a0 + b);", "float s = a0;",
+     "test_oracle_transport.py::test_tiny_phantom_primary_brute_force"),
+    ("type_order", "if (x < pe + coh) {", "if (x < pe + inc) {",
+     "test_oracle_transport.py::test_interaction_fractions"),
+    ("cone_solid_angle", "float ct = 1.0f - rng_u(r) * P->omc;",
+     "float ct = 1.0f - rng_u(r) * rng_u(r) * P->omc;",
+     "test_oracle_transport.py::test_source_multinomial_vacuum"),
+    ("panel_axis_sign", "P->eu[0] = -sb;", "P->eu[0] = sb;",
+     "test_oracle_transport.py::test_detector_pencil_rays"),
+    ("philox_weyl", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;",
+     "test_oracle_rng.py::test_philox_matches_rocrand"),
+    ("photo_z4", "C_PE * z * z * z / (e * e * e)", "C_PE * z * z * z * z / (e * e * e)",
+     "test_oracle_xs.py::test_photoelectric_form"),
+    ("kn_term_sign", "(t1 + t2 - t3)", "(t1 - t2 + t3)",
+     "test_oracle_xs.py::test_sigma_kn_vs_quadrature"),
+    ("coh_series_term", "4.0L / (n + 3));", "4.0L / (n + 2));",
+     "test_oracle_xs.py::test_coherent_vs_quadrature"),
+    ("lerp_sign", "return t[j] + f * (t[j + 1] - t[j]);", "return t[j] + f * (t[j] - t[j + 1]);",
+     "test_oracle_transport.py::test_beer_lambert_slab"),
+    ("tally_grid", "int su = iu / (g->nu / g->snu)", "int su = iu % g->snu",
+     "test_oracle_transport.py::test_scatter_binning"),
+]
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    d = tempfile.mkdtemp(prefix="mco_mut_")
+    yield d
+    shutil.rmtree(d, ignore_errors=True)
+
+
+@pytest.mark.parametrize("name,orig,bad,pin", CASES, ids=[c[0] for c in CASES])
+def test_pin_catches_planted_mistake(workdir, name, orig, bad, pin):
+    src = open(os.path.join(ROOT, "oracle", "mco.c")).read()
+    assert src.count(orig) == 1, f"mutation anchor not unique/present: {orig!r}"
+    d = os.path.join(workdir, name)
+    os.makedirs(d, exist_ok=True)
+    shutil.copy(os.path.join(ROOT, "oracle", "mco.h"), d)
+    with open(os.path.join(d, "mco.c"), "w") as f:
+        f.write(src.replace(orig, bad))
+    lib = os.path.join(d, "libmut.so")
+    subprocess.run(["gcc", *obuild.CFLAGS, "-o", lib, os.path.join(d, "mco.c"), "-lm"],
+                   check=True)
+    env = dict(os.environ, MCO_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, pin)], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 1 and "failed" in r.stdout, (name, r.stdout[-2000:])
