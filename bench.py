@@ -1,0 +1,174 @@
+"""Benchmark: photon histories per second of one MC forward projection on one GPU.
+
+Workload (default): 256^3 voxel phantom at 0.5 mm with 20 random ellipsoids of
+water / aluminium / bone-like calcium mix (densities 0.9 - 2.7 g/cm^3) in air,
+150 kVp Kramers spectrum behind 2 mm Al in 1 keV bins, source 500 mm from the
+axis, 512 x 512 panel of 0.4 mm at 1000 mm, 0.5 mm march step, 1e8 photons per
+projection; fp32 transport, int64 fixed-point tallies.  Inputs are resident in
+GPU memory before the timed region.  A "step" is one whole projection:
+clearing both images and the transport kernel over all photons.
+
+Output: one JSON line (metric, value, roofline of the transport kernel, CPU
+oracle baseline).  `python bench.py --gpus N` with N > 1 exits: this build
+measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+GATHER_BYTES_PER_STEP = 5        # uint8 material id + fp32 density per voxel lookup
+TALLY_BYTES = 8                  # one int64 atomic add per detected photon
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, seconds):
+    """The oracle, unchanged, on the host cores over a bounded photon sample."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    o = oracle.Oracle()
+    o.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
+    o.set_geometry(**w["geometry"])
+    o.set_spectrum(*w["spectrum"])
+    n0 = 20_000 * threads
+    t = time.perf_counter()
+    o.project(w["angle"], n0, w["seed"], threads=threads)
+    dt = time.perf_counter() - t
+    n = int(min(max(n0, n0 * seconds / max(dt, 1e-6)), 1e8))
+    t = time.perf_counter()
+    o.project(w["angle"], n, w["seed"], threads=threads)
+    dt = time.perf_counter() - t
+    return dict(value=n / dt, unit="photon histories/s", cores=threads, kind="oracle",
+                sample=f"photons 0..{n - 1} of the same projection ({n / w['n_photons']:.2%} of "
+                       f"one step), {dt:.1f} s wall on {threads} host threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ellipsoids256_poly")
+    ap.add_argument("--photons", type=int, default=0, help="override photons per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(projections and photon ranges shard without communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_13191_amd import inputs, mcx
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+
+    log("generating workload", args.workload)
+    w = inputs.workload(args.workload)
+    n = args.photons or w["n_photons"]
+    g = mcx.Projector(0)
+    g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
+    g.set_geometry(**w["geometry"])
+    g.set_spectrum(*w["spectrum"])
+    geo = w["geometry"]
+    dev = torch.device("cuda:0")
+    prim = torch.empty((geo["nv"], geo["nu"]), dtype=torch.int64, device=dev)
+    scat = torch.empty((geo["snv"], geo["snu"]), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"], prim, scat, stream)
+
+    # exact algorithmic work of one step (untimed counting pass)
+    log("counting pass")
+    g.stats(True)
+    step()
+    torch.cuda.synchronize()
+    st = g.stats()
+    g.stats(False)
+    alg_bytes = st["steps"] * GATHER_BYTES_PER_STEP + \
+        (st["primary_hits"] + st["scatter_hits"]) * TALLY_BYTES
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    log("timed", args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    launch_s = float(np.mean(step_ms)) * 1e-3
+    achieved = alg_bytes / launch_s / 1e9
+    log(f"{n * args.steps / wall:.4g} histories/s, {launch_s * 1e3:.2f} ms per step (events), "
+        f"steps/history {st['steps'] / max(st['histories'], 1):.1f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": "photon histories/s on 1 GPU (one cone-beam MC projection)",
+        "value": n * args.steps / wall,
+        "unit": "photon histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "phantom": "256^3 voxels at 0.5 mm, 20 random ellipsoids (water, Al, bone-Ca; "
+                       "0.9-2.7 g/cm^3) in air" if args.workload == "ellipsoids256_poly"
+                       else args.workload,
+            "spectrum": f"{len(w['spectrum'][0])} bins",
+            "detector": f"{geo['nu']}x{geo['nv']} at {geo['pu_mm']} mm, scatter "
+                        f"{geo['snu']}x{geo['snv']}",
+            "photons_per_step": n,
+            "step_mm": geo["step_mm"],
+            "tallies": "int64 fixed point",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "transport_kernel",
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "launch_ms": launch_s * 1e3,
+            "steps_per_history": st["steps"] / max(st["histories"], 1),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * mcx.h -- C ABI of libmcx, the MI355X (gfx950) Monte Carlo photon-transport
+ * forward projector for flat-panel cone-beam CT scatter estimation
+ * (Alsaffar, Kiess, Sun, Simon, arXiv 2201.13191).
+ *
+ * The library estimates, for one projection angle of a circular cone-beam
+ * scan, the primary image Ip (photons reaching the panel without interacting,
+ * the quantity of eq. (7)) and the scatter image Is (photons reaching it after
+ * one or more Compton / Rayleigh events, the quantity of eq. (6)), by analog
+ * Monte Carlo transport (section II-A): cone-beam point source, binned
+ * polychromatic spectrum (energy bins, section II-A below eq. (7)),
+ * fixed-step ray march through a voxel object (section II-C-2), photoelectric
+ * absorption, Rayleigh scattering (eq. (2)), Compton scattering (eq. (1) with
+ * S = 1, sampled by Kahn's method), 1 keV .. 1 MeV.
+ *
+ * Conventions
+ *   - Every function returns an mc_status: 0 on success, < 0 on error; the
+ *     context keeps a message for mc_last_error.  No C++ exception crosses
+ *     the ABI.
+ *   - A context is bound to one HIP device and is not thread-safe: use one
+ *     context per host thread.
+ *   - Host input pointers are only read during the call (data is copied).
+ *     Output buffers are owned by the caller.
+ *   - "_async" functions take device pointers and a hipStream_t passed as
+ *     void* (NULL = the legacy default stream) and return once the work is
+ *     queued; the buffers must stay valid until the stream reaches it.
+ *   - Setters (materials, phantom, geometry, spectrum, response) synchronise
+ *     the device before replacing device-side state.
+ *   - Tallies are signed 64-bit fixed point, Q43.20: one unit is 2^-20 keV of
+ *     detector response (mc_tally_scale()).  Integer addition is exact, so an
+ *     image does not depend on the order photons are processed: one seed gives
+ *     one bitwise result, on any launch configuration.
+ *
+ * Geometry (reading of section II-A; the paper gives the scanner parameters
+ * but no frame): rotation axis z; at angle b the source sits at
+ * sod*(cos b, sin b, 0), the panel is perpendicular to the central ray at
+ * distance sdd, u runs along (-sin b, cos b, 0) and v along +z; pixel (iu, iv)
+ * covers u in [-nu*pu/2 + iu*pu, +pu), v likewise; images are [nv][nu],
+ * iu fastest.  The phantom is centred on the origin, x fastest ([nz][ny][nx]).
+ * Outside the phantom box is vacuum.
+ */
+#ifndef MCX_H
+#define MCX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mc_status;
+
+#define MC_OK 0
+#define MC_E_INVALID_ARG (-1) /* argument out of range / null pointer           */
+#define MC_E_STATE (-2)       /* phantom, geometry or spectrum not set         */
+#define MC_E_OOM (-3)         /* device or host allocation failed               */
+#define MC_E_OVERFLOW (-4)    /* n_photons * max eta * 2^20 could reach 2^63     */
+#define MC_E_DEVICE (-6)      /* HIP runtime error (message has its text)       */
+
+/* mc_geometry.flags */
+#define MC_NO_SCATTER 1u      /* every interaction absorbs: pure attenuation    */
+
+/* processes of mc_test_sample */
+#define MC_PROC_SOURCE_ENERGY 0
+#define MC_PROC_RAYLEIGH 1
+#define MC_PROC_COMPTON 2
+#define MC_PROC_SOURCE_DIR 3
+
+/* end codes of mc_debug_histories */
+#define MC_END_PRIMARY 0
+#define MC_END_SCATTER 1
+#define MC_END_MISSED 2
+#define MC_END_PHOTO 3
+#define MC_END_CUTOFF 4
+#define MC_END_CAP 5
+
+typedef struct mc_ctx mc_ctx;
+
+/* Material of the voxel object: effective Z (photoelectric Z^3 scaling and the
+ * Rayleigh form factor's screening radius) and electrons per nucleon Z/A. */
+typedef struct mc_material {
+    float z_eff;       /* 1 .. 100                                   */
+    float z_over_a;    /* (0, 1.01]                                  */
+    float rho_default; /* nominal density, g/cm^3 (informational)    */
+    char name[16];
+} mc_material;
+
+/* Scanner geometry and transport knobs (scan parameters of section III;
+ * step size of section II-C-2). */
+typedef struct mc_geometry {
+    float sod_mm;      /* source - rotation axis distance, > 0            */
+    float sdd_mm;      /* source - panel distance, > sod                  */
+    int32_t nu, nv;    /* panel pixels, 1 .. 16384                        */
+    float pu_mm, pv_mm;
+    int32_t snu, snv;  /* scatter grid; nu % snu == 0 and nv % snv == 0   */
+    float step_mm;     /* fixed ray-march step, > 0                        */
+    uint32_t flags;    /* MC_NO_SCATTER                                    */
+} mc_geometry;
+
+/* Counters accumulated by projections run while statistics are enabled. */
+typedef struct mc_stats {
+    uint64_t histories;
+    uint64_t steps;        /* voxel lookups of the march                 */
+    uint64_t flights;
+    uint64_t photo, rayleigh, compton;
+    uint64_t primary_hits, scatter_hits;
+    uint64_t cutoff_kills, cap_hits;
+} mc_stats;
+
+/* Create a context on HIP device `device`; allocates only small buffers.
+ * device = -1 creates a host-only context: setters validate their arguments
+ * and mc_get_tables works, anything that needs the GPU returns MC_E_STATE. */
+mc_status mc_create(mc_ctx **out, int device);
+void mc_destroy(mc_ctx *ctx);
+/* Message of the last failing call on this context (never NULL). */
+const char *mc_last_error(const mc_ctx *ctx);
+
+/* Replace the material set (1 .. 16 entries).  The default set is
+ * 0 air, 1 water, 2 aluminium, 3 bone-like calcium mix, 4 iron.
+ * Cross-section tables are regenerated at the next projection. */
+mc_status mc_set_materials(mc_ctx *ctx, const mc_material *m, int n_mat);
+
+/* Voxel object (section II-A, voxelised object): ids[nz][ny][nx] material
+ * index, rho_gcc[nz][ny][nx] density g/cm^3 (finite, 0 .. 1000), cube voxel
+ * of edge voxel_mm.  nx*ny*nz < 2^31.  Copied to the device. */
+mc_status mc_load_phantom(mc_ctx *ctx, const uint8_t *ids, const float *rho_gcc, int nx,
+                          int ny, int nz, float voxel_mm);
+
+mc_status mc_set_geometry(mc_ctx *ctx, const mc_geometry *g);
+
+/* Polychromatic source as energy bins (the N bins of eq. (6)): bin energies
+ * e_keV in [1, 1000] and weights w >= 0 with a positive sum.  A photon's
+ * energy is the energy of a bin drawn with probability w_k / sum(w). */
+mc_status mc_set_spectrum(mc_ctx *ctx, const float *e_keV, const float *w, int n_bins);
+
+/* Detector energy response eta(E) (eq. (3)/(7)) on the 1 keV grid
+ * E_j = 1 + j keV, n >= 1 values (the last one repeats beyond n).  Default
+ * eta(E) = E (energy integrating).  eta = 1 counts photons. */
+mc_status mc_set_detector_response(mc_ctx *ctx, const float *eta, int n);
+
+/* One projection, blocking: simulates photons 0 .. n_photons-1 (emitted into
+ * the cone circumscribing the panel) with Philox key `seed`, and writes the
+ * Q43.20 tallies to host arrays primary[nv*nu] and scatter[snv*snu]. */
+mc_status mc_project(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t seed,
+                     int64_t *primary, int64_t *scatter);
+
+/* Stream-ordered: clears d_primary / d_scatter (device), then simulates
+ * photons 0 .. n_photons-1 into them. */
+mc_status mc_project_async(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t seed,
+                           int64_t *d_primary, int64_t *d_scatter, void *stream);
+
+/* Stream-ordered: ADDS the tallies of photons first .. first+n-1 into
+ * d_primary / d_scatter (no clearing).  Splitting a range into pieces gives
+ * bitwise the same sum. */
+mc_status mc_project_range_async(mc_ctx *ctx, float angle_rad, uint64_t first, uint64_t n,
+                                 uint64_t seed, int64_t *d_primary, int64_t *d_scatter,
+                                 void *stream);
+
+/* Per-history record of photons first .. first+m-1 (blocking, host outputs,
+ * any of them may be NULL): scatterings, march steps, end code (MC_END_*),
+ * and the type of the first interaction (0 none, 1 photo, 2 Rayleigh,
+ * 3 Compton). */
+mc_status mc_debug_histories(mc_ctx *ctx, float angle_rad, uint64_t first, uint64_t m,
+                             uint64_t seed, uint16_t *n_int, uint32_t *steps,
+                             uint8_t *end_code, uint8_t *first_type);
+
+/* GPU sampler hook (blocking, host outputs): n samples of one process, sample
+ * i using photon id i of `seed`.  SOURCE_ENERGY: e_out = birth energy.
+ * SOURCE_DIR: cos_out = cosine of the birth direction to the central ray.
+ * RAYLEIGH / COMPTON at e_keV in `material`: cos_out, e_out = outgoing
+ * cosine and energy. */
+mc_status mc_test_sample(mc_ctx *ctx, int process, int material, float e_keV, uint64_t n,
+                         uint64_t seed, float *cos_out, float *e_out);
+
+/* Statistics: enable (1) or disable (0) counting in later projections;
+ * mc_get_stats copies and clears the counters (synchronises the device). */
+mc_status mc_set_stats(mc_ctx *ctx, int enable);
+mc_status mc_get_stats(mc_ctx *ctx, mc_stats *out);
+
+/* Host-side cross-section tables exactly as the transport uses them:
+ * fp32 mu/rho [cm^2/g] per material on E_j = 1 + j keV, arrays [n_mat][J],
+ * and eta[J].  Pass NULL arrays to query J.  Needs the spectrum. */
+mc_status mc_get_tables(mc_ctx *ctx, int *J, float *pe, float *coh, float *inc, float *eta);
+
+/* Launch shape of the transport kernel (0 = automatic): threads per block
+ * (64 .. 1024, multiple of 64), blocks per compute unit, and march steps
+ * per scheduling round.  Results never depend on these. */
+mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int steps_per_round);
+
+/* keV per least significant bit of a tally: 2^-20. */
+double mc_tally_scale(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,295 @@
+"""ctypes binding of libmcx (include/mcx.h): argument marshalling only.
+
+Every function of the C ABI is exposed under the same name (mc_create,
+mc_load_phantom, mc_set_geometry, mc_set_spectrum, mc_project, ...); the
+`Projector` class bundles one context.  All transport runs in the library's
+HIP kernels; there is no CPU fallback: if libmcx.so is missing or cannot be
+loaded, every call raises.  PyTorch, when used, only supplies device memory
+(tensor data pointers) and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcx.so")
+
+MC_OK, MC_E_INVALID_ARG, MC_E_STATE, MC_E_OOM, MC_E_OVERFLOW, MC_E_DEVICE = 0, -1, -2, -3, -4, -6
+MC_NO_SCATTER = 1
+MC_PROC_SOURCE_ENERGY, MC_PROC_RAYLEIGH, MC_PROC_COMPTON, MC_PROC_SOURCE_DIR = 0, 1, 2, 3
+MC_END_PRIMARY, MC_END_SCATTER, MC_END_MISSED, MC_END_PHOTO, MC_END_CUTOFF, MC_END_CAP = range(6)
+
+EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_load_phantom",
+           "mc_set_geometry", "mc_set_spectrum", "mc_set_detector_response", "mc_project",
+           "mc_project_async", "mc_project_range_async", "mc_debug_histories", "mc_test_sample",
+           "mc_set_stats", "mc_get_stats", "mc_get_tables", "mc_set_launch", "mc_tally_scale"]
+
+
+class mc_material(C.Structure):
+    _fields_ = [("z_eff", C.c_float), ("z_over_a", C.c_float),
+                ("rho_default", C.c_float), ("name", C.c_char * 16)]
+
+
+class mc_geometry(C.Structure):
+    _fields_ = [("sod_mm", C.c_float), ("sdd_mm", C.c_float),
+                ("nu", C.c_int32), ("nv", C.c_int32),
+                ("pu_mm", C.c_float), ("pv_mm", C.c_float),
+                ("snu", C.c_int32), ("snv", C.c_int32),
+                ("step_mm", C.c_float), ("flags", C.c_uint32)]
+
+
+class mc_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "histories", "steps", "flights", "photo", "rayleigh", "compton",
+        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits")]
+
+
+class MCXError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmcx status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libmcx.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MCXError(MC_E_STATE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P, U64, F, I = C.c_void_p, C.c_uint64, C.c_float, C.c_int
+    sig = {
+        "mc_create": ([C.POINTER(P), I], I),
+        "mc_destroy": ([P], None),
+        "mc_last_error": ([P], C.c_char_p),
+        "mc_set_materials": ([P, C.POINTER(mc_material), I], I),
+        "mc_load_phantom": ([P, P, P, I, I, I, F], I),
+        "mc_set_geometry": ([P, C.POINTER(mc_geometry)], I),
+        "mc_set_spectrum": ([P, P, P, I], I),
+        "mc_set_detector_response": ([P, P, I], I),
+        "mc_project": ([P, F, U64, U64, P, P], I),
+        "mc_project_async": ([P, F, U64, U64, P, P, P], I),
+        "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
+        "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
+        "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
+        "mc_set_stats": ([P, I], I),
+        "mc_get_stats": ([P, C.POINTER(mc_stats)], I),
+        "mc_get_tables": ([P, C.POINTER(I), P, P, P, P], I),
+        "mc_set_launch": ([P, I, I, I], I),
+        "mc_tally_scale": ([], C.c_double),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _np(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    return C.c_void_p(t if isinstance(t, int) else t.data_ptr())
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return C.c_void_p(s)
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---- the C ABI under its own names -------------------------------------------------
+def mc_create(device=0):
+    h = C.c_void_p()
+    rc = load().mc_create(C.byref(h), device)
+    if rc:
+        raise MCXError(rc, f"mc_create(device={device}) failed")
+    return h
+
+
+def mc_destroy(ctx):
+    load().mc_destroy(ctx)
+
+
+def mc_last_error(ctx):
+    return load().mc_last_error(ctx).decode()
+
+
+def _check(ctx, rc):
+    if rc:
+        raise MCXError(rc, mc_last_error(ctx))
+
+
+def mc_set_materials(ctx, materials):
+    arr = (mc_material * len(materials))()
+    for i, m in enumerate(materials):
+        arr[i] = mc_material(m["z_eff"], m["z_over_a"], m.get("rho_default", 1.0),
+                             m.get("name", "").encode()[:15])
+    _check(ctx, load().mc_set_materials(ctx, arr, len(materials)))
+
+
+def mc_load_phantom(ctx, ids, rho, voxel_mm):
+    ids = np.ascontiguousarray(ids, dtype=np.uint8)
+    rho = np.ascontiguousarray(rho, dtype=np.float32)
+    nz, ny, nx = ids.shape
+    _check(ctx, load().mc_load_phantom(ctx, _np(ids), _np(rho), nx, ny, nz, float(voxel_mm)))
+
+
+def mc_set_geometry(ctx, sod_mm, sdd_mm, nu, nv, pu_mm, pv_mm, step_mm, snu=None, snv=None,
+                    flags=0):
+    g = mc_geometry(sod_mm, sdd_mm, nu, nv, pu_mm, pv_mm, snu or nu, snv or nv, step_mm, flags)
+    _check(ctx, load().mc_set_geometry(ctx, C.byref(g)))
+    return g
+
+
+def mc_set_spectrum(ctx, e_kev, w):
+    e = np.ascontiguousarray(e_kev, dtype=np.float32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(ctx, load().mc_set_spectrum(ctx, _np(e), _np(w), len(e)))
+
+
+def mc_set_detector_response(ctx, eta):
+    eta = np.ascontiguousarray(eta, dtype=np.float32)
+    _check(ctx, load().mc_set_detector_response(ctx, _np(eta), len(eta)))
+
+
+def mc_project(ctx, angle, n_photons, seed, primary, scatter):
+    """Blocking; primary/scatter are host int64 numpy arrays written in place."""
+    assert primary.dtype == np.int64 and scatter.dtype == np.int64
+    assert primary.flags.c_contiguous and scatter.flags.c_contiguous
+    _check(ctx, load().mc_project(ctx, angle, n_photons, seed, _np(primary), _np(scatter)))
+
+
+def mc_project_async(ctx, angle, n_photons, seed, d_primary, d_scatter, stream=None):
+    _check(ctx, load().mc_project_async(ctx, angle, n_photons, seed, _dev(d_primary),
+                                        _dev(d_scatter), _stream(stream)))
+
+
+def mc_project_range_async(ctx, angle, first, n, seed, d_primary, d_scatter, stream=None):
+    _check(ctx, load().mc_project_range_async(ctx, angle, first, n, seed, _dev(d_primary),
+                                              _dev(d_scatter), _stream(stream)))
+
+
+def mc_debug_histories(ctx, angle, first, m, seed):
+    n_int = np.zeros(m, np.uint16)
+    steps = np.zeros(m, np.uint32)
+    end = np.zeros(m, np.uint8)
+    first_t = np.zeros(m, np.uint8)
+    _check(ctx, load().mc_debug_histories(ctx, angle, first, m, seed, _np(n_int), _np(steps),
+                                          _np(end), _np(first_t)))
+    return n_int, steps, end, first_t
+
+
+def mc_test_sample(ctx, process, material, e_kev, n, seed):
+    cos = np.zeros(n, np.float32)
+    e = np.zeros(n, np.float32)
+    _check(ctx, load().mc_test_sample(ctx, process, material, e_kev, n, seed, _np(cos), _np(e)))
+    return cos, e
+
+
+def mc_set_stats(ctx, enable):
+    _check(ctx, load().mc_set_stats(ctx, int(bool(enable))))
+
+
+def mc_get_stats(ctx):
+    s = mc_stats()
+    _check(ctx, load().mc_get_stats(ctx, C.byref(s)))
+    return {n: getattr(s, n) for n, _ in mc_stats._fields_}
+
+
+def mc_get_tables(ctx, n_mat):
+    J = C.c_int()
+    _check(ctx, load().mc_get_tables(ctx, C.byref(J), None, None, None, None))
+    J = J.value
+    pe, coh, inc = (np.zeros((n_mat, J), np.float32) for _ in range(3))
+    eta = np.zeros(J, np.float32)
+    _check(ctx, load().mc_get_tables(ctx, C.byref(C.c_int()), _np(pe), _np(coh), _np(inc),
+                                     _np(eta)))
+    return pe, coh, inc, eta
+
+
+def mc_set_launch(ctx, block=0, blocks_per_cu=0, steps_per_round=0):
+    _check(ctx, load().mc_set_launch(ctx, block, blocks_per_cu, steps_per_round))
+
+
+def mc_tally_scale():
+    return load().mc_tally_scale()
+
+
+# ---- convenience wrapper ---------------------------------------------------------
+class Projector:
+    """One libmcx context with its geometry remembered for image shapes."""
+
+    def __init__(self, device=0):
+        self.ctx = mc_create(device)
+        self.geometry = None
+
+    def close(self):
+        if self.ctx:
+            mc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_materials(self, mats):
+        mc_set_materials(self.ctx, mats)
+
+    def load_phantom(self, ids, rho, voxel_mm):
+        mc_load_phantom(self.ctx, ids, rho, voxel_mm)
+
+    def set_geometry(self, **g):
+        geo = mc_set_geometry(self.ctx, g["sod_mm"], g["sdd_mm"], g["nu"], g["nv"], g["pu_mm"],
+                              g["pv_mm"], g["step_mm"], g.get("snu"), g.get("snv"),
+                              g.get("flags", 0))
+        self.geometry = dict(g, snu=geo.snu, snv=geo.snv)
+
+    def set_spectrum(self, e, w):
+        mc_set_spectrum(self.ctx, e, w)
+
+    def set_detector_response(self, eta):
+        mc_set_detector_response(self.ctx, eta)
+
+    def images(self):
+        g = self.geometry
+        return (np.zeros((g["nv"], g["nu"]), np.int64), np.zeros((g["snv"], g["snu"]), np.int64))
+
+    def project(self, angle, n, seed):
+        p, s = self.images()
+        mc_project(self.ctx, angle, n, seed, p, s)
+        return p, s
+
+    def debug_histories(self, angle, first, m, seed):
+        return mc_debug_histories(self.ctx, angle, first, m, seed)
+
+    def test_sample(self, process, material, e_kev, n, seed):
+        return mc_test_sample(self.ctx, process, material, e_kev, n, seed)
+
+    def tables(self, n_mat):
+        return mc_get_tables(self.ctx, n_mat)
+
+    def set_launch(self, block=0, blocks_per_cu=0, steps_per_round=0):
+        mc_set_launch(self.ctx, block, blocks_per_cu, steps_per_round)
+
+    def stats(self, enable=None):
+        if enable is not None:
+            mc_set_stats(self.ctx, enable)
+            return None
+        return mc_get_stats(self.ctx)

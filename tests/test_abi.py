@@ -1,0 +1,124 @@
+"""Host-side checks of libmcx: it loads, exports every function include/mcx.h
+declares, validates arguments in a host-only context, and builds the same
+fp32 cross-section tables as the oracle (no kernel is launched here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13191_amd import inputs, mcx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mcx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mcx.LIB_PATH):
+        pytest.fail("libmcx.so is not built (run __graft_entry__.build())")
+    return mcx.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mcx.EXPORTS)
+
+
+def test_tally_scale(lib):
+    assert mcx.mc_tally_scale() == 2.0 ** -20
+
+
+@pytest.fixture
+def host_ctx(lib):
+    ctx = mcx.mc_create(-1)
+    yield ctx
+    mcx.mc_destroy(ctx)
+
+
+def test_host_context_validation(host_ctx):
+    ctx = host_ctx
+    ids, rho = inputs.box_phantom(4, 4, 4, 1, 1.0)
+    bad = rho.copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_load_phantom(ctx, ids, bad, 1.0)
+    assert e.value.code == mcx.MC_E_INVALID_ARG
+    bad[1, 2, 3] = np.inf
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_load_phantom(ctx, ids, bad, 1.0)
+    # valid phantom: validated, then refused for lack of a device
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_load_phantom(ctx, ids, rho, 1.0)
+    assert e.value.code == mcx.MC_E_STATE
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_geometry(ctx, 500, 400, 10, 10, 1, 1, 0.5)        # sdd < sod
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_geometry(ctx, 500, 1000, 10, 10, 1, 1, 0.5, snu=3)
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_geometry(ctx, 500, 1000, 10, 10, 1, 1, 0.0)
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_geometry(ctx, 500, 1000, 10, 10, 1, 1, 0.5, flags=8)
+    mcx.mc_set_geometry(ctx, 500, 1000, 10, 10, 1, 1, 0.5, snu=5, snv=2)
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_spectrum(ctx, [1001.0], [1.0])
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_spectrum(ctx, [60.0, 70.0], [0.0, 0.0])
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_spectrum(ctx, [60.0], [np.nan])
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_materials(ctx, [dict(z_eff=0.5, z_over_a=0.5)])
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_set_launch(ctx, block=100)
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_get_tables(ctx, 5)                                    # no spectrum yet
+    assert e.value.code == mcx.MC_E_STATE
+    assert mcx.load().mc_create(None, 0) == mcx.MC_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("spec", ["mono60", "kramers150", "mono1000", "mono1.5"])
+def test_tables_bitwise_equal_oracle(host_ctx, spec):
+    if spec == "mono60":
+        e, w = inputs.mono_spectrum(60.0)
+    elif spec == "kramers150":
+        e, w = inputs.kramers_spectrum(150, 2.0)
+    elif spec == "mono1000":
+        e, w = inputs.mono_spectrum(1000.0)
+    else:
+        e, w = inputs.mono_spectrum(1.5)
+    mcx.mc_set_spectrum(host_ctx, e, w)
+    got = mcx.mc_get_tables(host_ctx, 5)
+    o = oracle.Oracle()
+    o.set_spectrum(e, w)
+    ref = o.tables(5)
+    for g, r in zip(got, ref):
+        assert g.shape == r.shape
+        assert np.array_equal(g.view(np.uint32), r.view(np.uint32))
+
+
+def test_tables_custom_materials_and_eta(host_ctx):
+    mats = [dict(z_eff=1.0, z_over_a=0.99), dict(z_eff=47.0, z_over_a=0.43),
+            dict(z_eff=82.0, z_over_a=0.396)]
+    eta = np.linspace(0.1, 5.0, 37).astype(np.float32)
+    e, w = inputs.kramers_spectrum(90, 1.0)
+    mcx.mc_set_materials(host_ctx, mats)
+    mcx.mc_set_spectrum(host_ctx, e, w)
+    mcx.mc_set_detector_response(host_ctx, eta)
+    got = mcx.mc_get_tables(host_ctx, 3)
+    o = oracle.Oracle()
+    o.set_materials(mats)
+    o.set_spectrum(e, w)
+    o.set_detector_response(eta)
+    ref = o.tables(3)
+    for g, r in zip(got, ref):
+        assert np.array_equal(g.view(np.uint32), r.view(np.uint32))

@@ -1,0 +1,252 @@
+"""GPU parity: libmcx (HIP, through the C ABI) against the CPU oracle.
+
+Same inputs, same seeds.  The bar (fp32 transport, int64 tallies): primary
+image rel-L2 <= 1e-3, scatter image rel-RMS (||a - b|| / ||b||) <= 0.5%,
+and >= 99.9% of histories with identical records (interaction count, march
+steps, end code, first interaction).  Both sides follow the same fully
+specified arithmetic, so in practice every case is bitwise equal; the
+tests report exact-match counts as well.
+
+Each test prints its case (and flushes) before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13191_amd import inputs, mcx
+
+pytestmark = pytest.mark.gpu
+
+PRIMARY_REL_L2 = 1e-3
+SCATTER_REL_RMS = 5e-3
+HISTORY_MATCH = 0.999
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on the MI355X box")
+    mcx.load()
+    return torch
+
+
+def rel_l2(a, b):
+    a = a.astype(np.float64)
+    b = b.astype(np.float64)
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return 0.0 if np.linalg.norm(a) == 0 else np.inf
+    return float(np.linalg.norm(a - b) / nb)
+
+
+def pair(ids, rho, h, geometry, spectrum, materials=None, eta=None):
+    o = oracle.Oracle()
+    g = mcx.Projector(0)
+    for side in (o, g):
+        if materials is not None:
+            side.set_materials(materials)
+        side.load_phantom(ids, rho, h)
+        side.set_geometry(**geometry)
+        side.set_spectrum(*spectrum)
+        if eta is not None:
+            side.set_detector_response(eta)
+    return o, g
+
+
+def check_images(name, pg, sg, po, so):
+    eq_p = int((pg != po).sum())
+    eq_s = int((sg != so).sum())
+    rp, rs = rel_l2(pg, po), rel_l2(sg, so)
+    say(name, f"primary mismatching pixels {eq_p} rel-L2 {rp:.3e}; scatter mismatching {eq_s} "
+              f"rel-RMS {rs:.3e}; totals {po.sum()} {so.sum()}")
+    assert rp <= PRIMARY_REL_L2, (name, rp)
+    assert rs <= SCATTER_REL_RMS, (name, rs)
+
+
+def check_histories(name, a, b):
+    same = np.ones(len(a[0]), bool)
+    for x, y in zip(a, b):
+        same &= (x == y)
+    frac = same.mean() if len(same) else 1.0
+    say(name, f"histories identical {same.sum()}/{len(same)}")
+    assert frac >= HISTORY_MATCH, (name, frac)
+
+
+def cyl():
+    return inputs.workload("cylinder64")
+
+
+# --------------------------------------------------------------------------------
+def test_samplers_match_oracle(gpu):
+    say("samplers")
+    w = cyl()
+    o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], inputs.kramers_spectrum())
+    n = 200_000
+    for proc, mat, e in [(mcx.MC_PROC_COMPTON, 2, 60.0), (mcx.MC_PROC_COMPTON, 1, 1000.0),
+                         (mcx.MC_PROC_COMPTON, 4, 1.0), (mcx.MC_PROC_RAYLEIGH, 1, 60.0),
+                         (mcx.MC_PROC_RAYLEIGH, 4, 3.3), (mcx.MC_PROC_SOURCE_ENERGY, 0, 0.0),
+                         (mcx.MC_PROC_SOURCE_DIR, 0, 0.0)]:
+        say("sampler", proc, mat, e)
+        cg, eg = g.test_sample(proc, mat, e, n, seed=17)
+        co, eo = o.test_sample(proc, mat, e, n, seed=17)
+        if proc != mcx.MC_PROC_SOURCE_ENERGY:
+            same = (cg.view(np.uint32) == co.view(np.uint32)).mean()
+            assert same >= HISTORY_MATCH, (proc, mat, e, same)
+            assert np.abs(cg - co).max() < 1e-6
+        if proc != mcx.MC_PROC_SOURCE_DIR:
+            assert (eg.view(np.uint32) == eo.view(np.uint32)).mean() >= HISTORY_MATCH
+
+
+def test_cylinder64_workload(gpu):
+    w = cyl()
+    say("cylinder64 1e6 photons, 60 keV, 128^2 panel")
+    o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"])
+    pg, sg = g.project(w["angle"], w["n_photons"], w["seed"])
+    po, so = o.project(w["angle"], w["n_photons"], w["seed"], threads=8)
+    check_images("cylinder64", pg, sg, po, so)
+    say("cylinder64 histories 0..2e5")
+    check_histories("cylinder64", g.debug_histories(0.0, 0, 200_000, 0),
+                    o.debug_histories(0.0, 0, 200_000, 0))
+
+
+def test_random_phantom_polychromatic_ragged(gpu):
+    rng = np.random.default_rng(7)
+    ids = rng.integers(0, 5, size=(16, 20, 24)).astype(np.uint8)
+    rho = rng.uniform(0.0, 3.0, size=ids.shape).astype(np.float32)
+    geo = dict(sod_mm=300.0, sdd_mm=700.0, nu=40, nv=30, pu_mm=2.5, pv_mm=3.0, snu=10, snv=5,
+               step_mm=0.7, flags=0)
+    say("random 24x20x16 phantom, 150 kVp, ragged 300007 photons, beta 1.234")
+    o, g = pair(ids, rho, 2.0, geo, inputs.kramers_spectrum(150, 2.0))
+    pg, sg = g.project(1.234, 300_007, 99)
+    po, so = o.project(1.234, 300_007, 99, threads=8)
+    check_images("random-poly", pg, sg, po, so)
+    check_histories("random-poly", g.debug_histories(1.234, 1000, 50_000, 99),
+                    o.debug_histories(1.234, 1000, 50_000, 99))
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 4097])
+def test_photon_counts(gpu, n):
+    w = cyl()
+    say("photon count", n)
+    o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"])
+    pg, sg = g.project(0.3, n, 5)
+    po, so = o.project(0.3, n, 5)
+    assert np.array_equal(pg, po) and np.array_equal(sg, so)
+
+
+EDGE = {
+    "vacuum": lambda: (*inputs.box_phantom(8, 8, 8, 0, 0.0), 1.0, {}, inputs.mono_spectrum(60.0)),
+    "single_voxel_iron": lambda: (*inputs.box_phantom(1, 1, 1, 4, 7.874), 20.0, {},
+                                  inputs.mono_spectrum(100.0)),
+    "no_scatter_slab": lambda: (*inputs.box_phantom(10, 64, 64, 1, 1.0), 1.0,
+                                {"flags": mcx.MC_NO_SCATTER}, inputs.mono_spectrum(20.7)),
+    "one_pixel_panel": lambda: (*inputs.cylinder_phantom(16, 2.0), 2.0,
+                                {"nu": 1, "nv": 1, "pu_mm": 50.0, "pv_mm": 50.0},
+                                inputs.mono_spectrum(60.0)),
+    "high_energy_iron": lambda: (*inputs.box_phantom(20, 20, 20, 4, 7.874), 2.0, {},
+                                 inputs.mono_spectrum(1000.0)),
+    "low_energy_cutoff": lambda: (*inputs.box_phantom(20, 20, 20, 1, 1.0), 0.5, {},
+                                  inputs.mono_spectrum(1.5)),
+    "thick_water_many_scatters": lambda: (*inputs.box_phantom(60, 60, 60, 1, 1.0), 2.0, {},
+                                          inputs.mono_spectrum(200.0)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+def test_edge_cases(gpu, case):
+    ids, rho, h, geo_over, spec = EDGE[case]()
+    geo = dict(sod_mm=500.0, sdd_mm=1000.0, nu=32, nv=24, pu_mm=3.0, pv_mm=4.0, snu=8, snv=6,
+               step_mm=0.5, flags=0)
+    geo.update(geo_over)
+    if geo["nu"] == 1:
+        geo["snu"] = geo["snv"] = 1
+    say("edge", case)
+    o, g = pair(ids, rho, h, geo, spec)
+    n = 100_000
+    pg, sg = g.project(0.5, n, 3)
+    po, so = o.project(0.5, n, 3, threads=8)
+    check_images(case, pg, sg, po, so)
+    check_histories(case, g.debug_histories(0.5, 0, 20_000, 3), o.debug_histories(0.5, 0, 20_000, 3))
+
+
+def test_launch_shape_invariance(gpu):
+    w = cyl()
+    say("launch shapes")
+    g = mcx.Projector(0)
+    g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
+    g.set_geometry(**w["geometry"])
+    g.set_spectrum(*inputs.kramers_spectrum(100, 1.0))
+    ref = g.project(0.7, 300_000, 11)
+    for block, bpc, spr in [(64, 1, 1), (128, 2, 7), (256, 0, 1024), (192, 3, 33), (64, 8, 64)]:
+        say("launch", block, bpc, spr)
+        g.set_launch(block, bpc, spr)
+        p, s = g.project(0.7, 300_000, 11)
+        assert np.array_equal(p, ref[0]) and np.array_equal(s, ref[1]), (block, bpc, spr)
+
+
+def test_async_range_split(gpu):
+    torch = gpu
+    w = cyl()
+    say("async range split")
+    g = mcx.Projector(0)
+    g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
+    g.set_geometry(**w["geometry"])
+    g.set_spectrum(*w["spectrum"])
+    dev = torch.device("cuda:0")
+    p = torch.zeros((128, 128), dtype=torch.int64, device=dev)
+    s = torch.zeros((128, 128), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    mcx.mc_project_async(g.ctx, 0.1, 400_000, 9, p, s, stream)
+    p2 = torch.zeros_like(p)
+    s2 = torch.zeros_like(s)
+    for a, b in [(0, 1), (1, 150_000), (150_000, 150_001), (150_001, 400_000)]:
+        mcx.mc_project_range_async(g.ctx, 0.1, a, b - a, 9, p2, s2, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(p, p2) and torch.equal(s, s2)
+    hp, hs = g.project(0.1, 400_000, 9)
+    assert np.array_equal(hp, p.cpu().numpy()) and np.array_equal(hs, s.cpu().numpy())
+
+
+def test_stats_match_oracle(gpu):
+    w = cyl()
+    say("stats")
+    o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], inputs.kramers_spectrum())
+    g.stats(True)
+    g.project(0.0, 200_000, 2)
+    sg = g.stats()
+    o.stats()
+    o.project(0.0, 200_000, 2)
+    so = o.stats()
+    say("stats", sg, so)
+    for k in sg:
+        assert abs(sg[k] - so[k]) <= max(2, 1e-3 * so[k]), k
+
+
+def test_errors(gpu):
+    say("errors")
+    g = mcx.Projector(0)
+    with pytest.raises(mcx.MCXError) as e:
+        p = np.zeros(4, np.int64)
+        mcx.mc_project(g.ctx, 0.0, 10, 0, p, p)
+    assert e.value.code == mcx.MC_E_STATE
+    ids, rho = inputs.box_phantom(4, 4, 4, 1, 1.0)
+    g.load_phantom(ids, rho, 1.0)
+    g.set_geometry(sod_mm=500.0, sdd_mm=1000.0, nu=10, nv=10, pu_mm=1.0, pv_mm=1.0,
+                   step_mm=0.5)
+    g.set_spectrum([60.0], [1.0])
+    with pytest.raises(mcx.MCXError) as e:
+        g.project(0.0, 2 ** 63 // (61 * 2 ** 20) + 10, 0)
+    assert e.value.code == mcx.MC_E_OVERFLOW
+    ids[0, 0, 0] = 7
+    g.load_phantom(ids, rho, 1.0)
+    with pytest.raises(mcx.MCXError) as e:
+        g.project(0.0, 10, 0)
+    assert e.value.code == mcx.MC_E_INVALID_ARG
