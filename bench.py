@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--photons", type=int, default=0, help="override photons per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (three times), "
+                         "to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -73,6 +76,15 @@ def main():
     from paper_2201_13191_amd import inputs, mcx
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+        return
 
     log("generating workload", args.workload)
     w = inputs.workload(args.workload)
