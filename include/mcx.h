@@ -156,6 +156,36 @@ mc_status mc_project_range_async(mc_ctx *ctx, float angle_rad, uint64_t first, u
                                  uint64_t seed, int64_t *d_primary, int64_t *d_scatter,
                                  void *stream);
 
+/* Add another voxel object (same rules as mc_load_phantom) for batches; its
+ * handle (>= 1) is written to *handle.  Handle 0 is the object of
+ * mc_load_phantom. */
+mc_status mc_phantom_add(mc_ctx *ctx, const uint8_t *ids, const float *rho_gcc, int nx, int ny,
+                         int nz, float voxel_mm, int *handle);
+
+/* One projection of a batch. */
+typedef struct mc_job {
+    int32_t phantom;           /* phantom handle                                   */
+    float angle_rad;
+    uint64_t n_photons;
+    uint64_t seed;
+    uint64_t primary_offset;   /* element offset of the job's [nv][nu] image in d_out   */
+    uint64_t scatter_offset;   /* element offset of the job's [snv][snu] image in d_out */
+} mc_job;
+
+#define MC_BATCH_GRAPH 1u      /* capture clear + transport in a hipGraph and replay it */
+
+/* Many projections (angles, phantoms of different sizes, photon counts) in
+ * one persistent launch, stream-ordered: clears d_out[0 .. out_elems) (device,
+ * int64), then simulates every job; each job's images are bitwise those of
+ * mc_project_async with the same phantom, angle, photon count and seed.  The
+ * projections of section III (many angles of one scan, independent of each
+ * other) are the intended use.  With MC_BATCH_GRAPH the clear and transport
+ * kernels are captured once into a graph (re-captured when buffers, job
+ * count, launch shape or context state change) and replayed; the job table
+ * itself is copied before each replay. */
+mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                           uint64_t out_elems, uint32_t flags, void *stream);
+
 /* Per-history record of photons first .. first+m-1 (blocking, host outputs,
  * any of them may be NULL): scatterings, march steps, end code (MC_END_*),
  * and the type of the first interaction (0 none, 1 photo, 2 Rayleigh,
@@ -182,10 +212,26 @@ mc_status mc_get_stats(mc_ctx *ctx, mc_stats *out);
  * and eta[J].  Pass NULL arrays to query J.  Needs the spectrum. */
 mc_status mc_get_tables(mc_ctx *ctx, int *J, float *pe, float *coh, float *inc, float *eta);
 
+/* Device layout of the voxel object, chosen at the next mc_load_phantom.
+ * AUTO: objects with <= 256 distinct (material, density) pairs are stored as
+ * one-byte palette codes (per-lane attenuation table for <= 32 entries,
+ * shared palette otherwise), others as material ids plus densities.  All
+ * layouts are bricked (8x4x4 voxels) and give bitwise the same images. */
+#define MC_LAYOUT_AUTO 0
+#define MC_LAYOUT_PALETTE_LANE 1
+#define MC_LAYOUT_PALETTE_SHARED 2
+#define MC_LAYOUT_GENERIC 3
+mc_status mc_set_layout(mc_ctx *ctx, int layout);
+/* Layout in use for the loaded object (never AUTO) and its palette size
+ * (0 for GENERIC). */
+mc_status mc_get_layout(mc_ctx *ctx, int *layout, int *palette_size);
+
 /* Launch shape of the transport kernel (0 = automatic): threads per block
- * (64 .. 1024, multiple of 64), blocks per compute unit, and march steps
- * per scheduling round.  Results never depend on these. */
-mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int steps_per_round);
+ * (64, 128, 192 or 256), resident blocks per compute unit, and the event
+ * batch: how many of a wave's 64 lanes must be waiting for an interaction or
+ * a panel crossing before the wave stops marching and handles them (1 .. 64).
+ * Results never depend on these. */
+mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int event_batch);
 
 /* keV per least significant bit of a tally: 2^-20. */
 double mc_tally_scale(void);

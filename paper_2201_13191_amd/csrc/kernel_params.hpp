@@ -19,19 +19,55 @@ struct ProjFrame {
     float omc;      // 1 - cos(half-angle of the cone circumscribing the panel)
 };
 
-struct KParams {
-    // voxel object, x fastest
-    const uint8_t *ids;
-    const float *rho;
+// Voxel representations on the device.  Voxels are stored in bricks of
+// kBx x kBy x kBz (x fastest inside a brick, bricks x fastest): a brick of
+// one-byte codes is one 128-byte cache line.
+constexpr int kBx = 8, kBy = 4, kBz = 4;
+constexpr int kBrick = kBx * kBy * kBz;
+
+enum Layout : int {
+    kPaletteLane = 0,    // byte = palette index; per-lane mu table of every palette entry
+    kPaletteShared = 1,  // byte = palette index; palette (id, rho) shared, per-lane mu per material
+    kGeneric = 2         // byte = material id, separate bricked fp32 density
+};
+
+// One voxel object as the march sees it.
+struct VoxelGrid {
+    const uint8_t *vox;        // bricked codes (palette index or material id)
+    const float *vrho;         // bricked densities (kGeneric only)
+    const uint8_t *pal_id;     // [n_pal] material of each palette entry
+    const float *pal_rho;      // [n_pal] density of each palette entry
+    int n_pal;
+    int layout;                // Layout of this object
     int nx, ny, nz;
+    int nbx, nby;              // bricks along x and y
+    uint32_t sy, sz;           // byte strides of one brick row (y) and one brick slab (z)
+    float cmax[3];             // nx - 1, ny - 1, nz - 1 as floats (voxel-coordinate clamp)
     float inv_h;
     float lo[3], hi[3];
+};
+
+// One projection of a batch: its frame, Philox key, photon count, images
+// and voxel object.
+struct JobDesc {
+    ProjFrame F;
+    uint32_t key0, key1;
+    uint64_t n;
+    unsigned long long *prim, *scat;
+    int grid;
+    int pad;
+};
+
+struct KParams {
+    // voxel object (single projection)
+    VoxelGrid G;
     // tables: [n_mat][J] mu/rho on E_j = 1 + j keV, eta[J]
     const float *pe, *coh, *inc, *eta;
     int J, n_mat;
     const double *rayl_b;      // [n_mat] Rayleigh screening constants
     const float *e_bin;        // [n_bins] bin energies
     const uint64_t *thr;       // [n_bins] cumulative thresholds on 32-bit draws
+    const uint32_t *guide;     // [256] first bin whose threshold exceeds i * 2^24
     int n_bins;
     // panel and march
     ProjFrame F;
@@ -41,10 +77,16 @@ struct KParams {
     // work
     uint64_t first, n;
     uint32_t key0, key1;
-    int steps_per_round;
+    int event_batch;           // lanes that must wait before a wave handles events
     unsigned long long *prim, *scat;     // int64 tallies (two's complement adds)
     unsigned long long *counter;         // next photon index (relative to first)
     unsigned long long *stats;           // mc_stats layout, or null
+    // batch: jobs run in order, each wave moving to the next job when the
+    // current one has no photons left
+    const JobDesc *jobs;
+    const VoxelGrid *grids;
+    unsigned long long *job_counters;    // [n_jobs] next photon of each job
+    int n_jobs;
     // per-history records (debug kernel only)
     uint16_t *dbg_nint;
     uint32_t *dbg_steps;

@@ -20,11 +20,16 @@
 #include "tables.hpp"
 
 namespace mcx {
-hipError_t launch_transport(const KParams &p, int grid, int block, bool stats, bool debug,
-                            hipStream_t stream);
+hipError_t launch_transport(const KParams &p, int layout, int grid, int block, bool stats,
+                            bool debug, hipStream_t stream);
 hipError_t launch_sample(const KParams &p, int process, int material, float e_kev, uint64_t n,
                          float *cos_out, float *e_out, hipStream_t stream);
-int transport_blocks_per_cu(int block, int n_mat, bool stats);
+int transport_blocks_per_cu(const KParams &p, int layout, int block, bool stats);
+hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int block, bool stats,
+                        hipStream_t stream);
+int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats);
+hipError_t launch_clear(unsigned long long *a, size_t na, unsigned long long *b, size_t nb,
+                        hipStream_t stream);
 }  // namespace mcx
 
 using namespace mcx;
@@ -32,7 +37,34 @@ using namespace mcx;
 namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
+constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
+constexpr int kDefaultEventBatch = 32;
 }  // namespace
+
+// One voxel object on the device: bricked one-byte codes (palette index, or
+// material id with a bricked density array when the object has more than 256
+// distinct (id, rho) pairs).
+struct Phantom {
+    int nx = 0, ny = 0, nz = 0, nbx = 0, nby = 0, nbz = 0;
+    float h = 0.0f;
+    int max_id = 0;
+    bool generic = false;
+    int n_pal = 0;
+    uint8_t *d_vox = nullptr;
+    float *d_vrho = nullptr;
+    unsigned char *d_pal = nullptr;     // 256 densities (f32) then 256 ids (u8)
+    bool loaded = false;
+
+    void release() {
+        if (d_vox) (void)hipFree(d_vox);
+        if (d_vrho) (void)hipFree(d_vrho);
+        if (d_pal) (void)hipFree(d_pal);
+        d_vox = nullptr;
+        d_vrho = nullptr;
+        d_pal = nullptr;
+        loaded = false;
+    }
+};
 
 struct mc_ctx {
     int device = 0;
@@ -43,13 +75,18 @@ struct mc_ctx {
     std::vector<mc_material> mats;
     std::vector<double> rayl_b;
 
-    // phantom
-    int nx = 0, ny = 0, nz = 0;
-    float h = 0.0f;
-    int max_id = 0;
-    uint8_t *d_ids = nullptr;
-    float *d_rho = nullptr;
+    // voxel objects: [0] is the one of mc_load_phantom, more from mc_phantom_add
+    std::vector<Phantom> phantoms = std::vector<Phantom>(1);
+    int layout_req = MC_LAYOUT_AUTO;
     bool have_phantom = false;
+
+    // batches: device job table, grid table, per-job counters, captured graph
+    void *d_batch = nullptr;
+    size_t d_batch_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+    unsigned generation = 0;             // bumped by every setter
 
     mc_geometry g{};
     bool have_geom = false;
@@ -70,6 +107,7 @@ struct mc_ctx {
     const float *dp_pe = nullptr, *dp_coh = nullptr, *dp_inc = nullptr, *dp_eta = nullptr;
     const float *dp_ebin = nullptr;
     const uint64_t *dp_thr = nullptr;
+    const uint32_t *dp_guide = nullptr;
     const double *dp_rb = nullptr;
 
     // control block: [0, kRing) photon counters, one per launch in turn so
@@ -82,7 +120,7 @@ struct mc_ctx {
     int64_t *d_img = nullptr;
     size_t d_img_elems = 0;
 
-    int block = 0, blocks_per_cu = 0, steps_per_round = 0;
+    int block = 0, blocks_per_cu = 0, event_batch = 0;
 };
 
 namespace {
@@ -117,6 +155,7 @@ const mc_material kDefaultMaterials[5] = {
 };
 
 void set_materials(mc_ctx *c, const mc_material *m, int n) {
+    ++c->generation;
     c->mats.assign(m, m + n);
     c->rayl_b.resize(n);
     for (int i = 0; i < n; ++i) c->rayl_b[i] = rayleigh_b(m[i].z_eff);
@@ -133,6 +172,7 @@ mc_status use_device(mc_ctx *c) {
 // no queued kernel still reads the old blob).
 mc_status refresh_tables(mc_ctx *c) {
     if (!c->tables_dirty) return MC_OK;
+    ++c->generation;
     const int n_mat = (int)c->mats.size();
     std::vector<Material> mm(n_mat);
     for (int i = 0; i < n_mat; ++i) mm[i] = {c->mats[i].z_eff, c->mats[i].z_over_a};
@@ -140,10 +180,16 @@ mc_status refresh_tables(mc_ctx *c) {
     build_tables(mm.data(), n_mat, J, c->eta_user.empty() ? nullptr : c->eta_user.data(),
                  (int)c->eta_user.size(), c->pe, c->coh, c->inc, c->eta);
     c->J = J;
-    // blob: rb[n_mat] f64 | thr[n_bins] u64 | pe | coh | inc [n_mat*J] | eta[J] | e_bin[n_bins]
+    // blob: rb[n_mat] f64 | thr[n_bins] u64 | pe | coh | inc [n_mat*J] | eta[J] |
+    //       e_bin[n_bins] | guide[256] u32
     const size_t nb = c->e_bin.size();
     const size_t tab = (size_t)n_mat * J;
-    const size_t bytes = n_mat * 8 + nb * 8 + (3 * tab + J + nb) * 4;
+    const size_t bytes = n_mat * 8 + nb * 8 + (3 * tab + J + nb + 256) * 4;
+    uint32_t guide[256];
+    for (uint32_t i = 0, k = 0; i < 256; ++i) {
+        while (c->thr[k] <= ((uint64_t)i << 24)) ++k;
+        guide[i] = k;
+    }
     std::vector<unsigned char> blob(bytes);
     size_t off = 0;
     auto put = [&](const void *src, size_t n) {
@@ -157,6 +203,7 @@ mc_status refresh_tables(mc_ctx *c) {
     put(c->inc.data(), tab * 4);
     put(c->eta.data(), (size_t)J * 4);
     put(c->e_bin.data(), nb * 4);
+    put(guide, sizeof guide);
     HIP_TRY(c, hipDeviceSynchronize());
     if (bytes > c->d_tables_bytes) {
         if (c->d_tables) (void)hipFree(c->d_tables);
@@ -175,55 +222,60 @@ mc_status refresh_tables(mc_ctx *c) {
     c->dp_inc = f + 2 * tab;
     c->dp_eta = f + 3 * tab;
     c->dp_ebin = f + 3 * tab + J;
+    c->dp_guide = (const uint32_t *)(f + 3 * tab + J + nb);
     c->tables_dirty = false;
     return MC_OK;
 }
 
-// Every precondition of a projection of n photons; fills the kernel params.
-mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t seed,
-                  KParams &p) {
-    if (!c->have_phantom || !c->have_geom || !c->have_spec)
-        return fail(c, MC_E_STATE, "phantom, geometry and spectrum must be set");
-    if (!std::isfinite(beta)) return fail(c, MC_E_INVALID_ARG, "angle must be finite");
-    if (c->max_id >= (int)c->mats.size())
-        return fail(c, MC_E_INVALID_ARG, "material id %d >= n_mat %d", c->max_id,
+int phantom_layout(const mc_ctx *c, const Phantom &ph) {
+    if (ph.generic) return kGeneric;
+    if (c->layout_req == MC_LAYOUT_PALETTE_SHARED || ph.n_pal > kMaxLanePalette)
+        return kPaletteShared;
+    return kPaletteLane;
+}
+
+mc_status check_phantom(mc_ctx *c, const Phantom &ph) {
+    if (ph.max_id >= (int)c->mats.size())
+        return fail(c, MC_E_INVALID_ARG, "material id %d >= n_mat %d", ph.max_id,
                     (int)c->mats.size());
-    const double hx = 0.5 * c->nx * c->h, hy = 0.5 * c->ny * c->h, hz = 0.5 * c->nz * c->h;
+    const double hx = 0.5 * ph.nx * ph.h, hy = 0.5 * ph.ny * ph.h, hz = 0.5 * ph.nz * ph.h;
     const double diag = std::sqrt(hx * hx + hy * hy + hz * hz);
     if (!(diag < c->g.sod_mm) || !(diag < (double)c->g.sdd_mm - c->g.sod_mm))
         return fail(c, MC_E_INVALID_ARG, "phantom must lie strictly between source and panel");
     if (2.0 * diag / c->g.step_mm > 4194304.0)
         return fail(c, MC_E_INVALID_ARG, "step too small for the phantom");
-    if (first + n < first) return fail(c, MC_E_INVALID_ARG, "photon range wraps");
-    mc_status rc = refresh_tables(c);
-    if (rc) return rc;
-    float eta_max = 0.0f;
-    for (float v : c->eta) eta_max = std::max(eta_max, v);
-    if ((long double)(first + n) * ((long double)eta_max * 1048576.0L + 1.0L) >=
-        9223372036854775807.0L)
-        return fail(c, MC_E_OVERFLOW, "tally could overflow int64");
+    return MC_OK;
+}
 
-    std::memset(&p, 0, sizeof p);
-    p.ids = c->d_ids;
-    p.rho = c->d_rho;
-    p.nx = c->nx; p.ny = c->ny; p.nz = c->nz;
-    p.inv_h = 1.0f / c->h;
-    const int nd[3] = {c->nx, c->ny, c->nz};
+VoxelGrid grid_of(const mc_ctx *c, const Phantom &ph) {
+    VoxelGrid G;
+    std::memset(&G, 0, sizeof G);
+    G.vox = ph.d_vox;
+    G.vrho = ph.d_vrho;
+    G.pal_rho = ph.d_pal ? (const float *)ph.d_pal : nullptr;
+    G.pal_id = ph.d_pal ? ph.d_pal + 256 * 4 : nullptr;
+    G.n_pal = ph.n_pal;
+    G.layout = phantom_layout(c, ph);
+    G.nx = ph.nx; G.ny = ph.ny; G.nz = ph.nz;
+    G.nbx = ph.nbx; G.nby = ph.nby;
+    G.sy = (uint32_t)ph.nbx * kBrick;
+    G.sz = (uint32_t)ph.nbx * ph.nby * kBrick;
+    G.cmax[0] = (float)(ph.nx - 1);
+    G.cmax[1] = (float)(ph.ny - 1);
+    G.cmax[2] = (float)(ph.nz - 1);
+    G.inv_h = 1.0f / ph.h;
+    const int nd[3] = {ph.nx, ph.ny, ph.nz};
     for (int a = 0; a < 3; ++a) {
-        p.hi[a] = 0.5f * ((float)nd[a] * c->h);
-        p.lo[a] = -p.hi[a];
+        G.hi[a] = 0.5f * ((float)nd[a] * ph.h);
+        G.lo[a] = -G.hi[a];
     }
-    p.pe = c->dp_pe; p.coh = c->dp_coh; p.inc = c->dp_inc; p.eta = c->dp_eta;
-    p.J = c->J;
-    p.n_mat = (int)c->mats.size();
-    p.rayl_b = c->dp_rb;
-    p.e_bin = c->dp_ebin;
-    p.thr = c->dp_thr;
-    p.n_bins = (int)c->e_bin.size();
-    // projection frame
-    const mc_geometry &g = c->g;
+    return G;
+}
+
+// Frame of the projection at angle beta (fp32 values from fp64 sin/cos).
+ProjFrame frame_of(const mc_geometry &g, float beta) {
+    ProjFrame F;
     const float cb = (float)std::cos((double)beta), sb = (float)std::sin((double)beta);
-    ProjFrame &F = p.F;
     F.S[0] = g.sod_mm * cb; F.S[1] = g.sod_mm * sb; F.S[2] = 0.0f;
     F.ax[0] = -cb; F.ax[1] = -sb; F.ax[2] = 0.0f;
     F.eu[0] = -sb; F.eu[1] = cb; F.eu[2] = 0.0f;
@@ -233,36 +285,80 @@ mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t se
     F.hv = 0.5f * ((float)g.nv * g.pv_mm);
     const double sdd = g.sdd_mm, hu = F.hu, hv = F.hv;
     F.omc = (float)(1.0 - sdd / std::sqrt(sdd * sdd + hu * hu + hv * hv));
+    return F;
+}
+
+mc_status check_overflow(mc_ctx *c, uint64_t n_max) {
+    float eta_max = 0.0f;
+    for (float v : c->eta) eta_max = std::max(eta_max, v);
+    if ((long double)n_max * ((long double)eta_max * 1048576.0L + 1.0L) >= 9223372036854775807.0L)
+        return fail(c, MC_E_OVERFLOW, "tally could overflow int64");
+    return MC_OK;
+}
+
+// Tables, panel and knobs shared by single and batched launches.
+void common_params(mc_ctx *c, KParams &p) {
+    std::memset(&p, 0, sizeof p);
+    p.pe = c->dp_pe; p.coh = c->dp_coh; p.inc = c->dp_inc; p.eta = c->dp_eta;
+    p.J = c->J;
+    p.n_mat = (int)c->mats.size();
+    p.rayl_b = c->dp_rb;
+    p.e_bin = c->dp_ebin;
+    p.thr = c->dp_thr;
+    p.guide = c->dp_guide;
+    p.n_bins = (int)c->e_bin.size();
+    const mc_geometry &g = c->g;
     p.sdd = g.sdd_mm; p.pu = g.pu_mm; p.pv = g.pv_mm; p.step = g.step_mm;
     p.nu = g.nu; p.nv = g.nv; p.snu = g.snu; p.snv = g.snv;
     p.bu = g.nu / g.snu; p.bv = g.nv / g.snv;
     p.flags = g.flags;
+    p.event_batch = c->event_batch > 0 ? c->event_batch : kDefaultEventBatch;
+    p.stats = c->d_ctl + kRing;
+}
+
+// Every precondition of a projection of n photons; fills the kernel params.
+mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t seed,
+                  KParams &p) {
+    if (!c->have_phantom || !c->have_geom || !c->have_spec)
+        return fail(c, MC_E_STATE, "phantom, geometry and spectrum must be set");
+    if (!std::isfinite(beta)) return fail(c, MC_E_INVALID_ARG, "angle must be finite");
+    const Phantom &ph = c->phantoms[0];
+    mc_status rc = check_phantom(c, ph);
+    if (rc) return rc;
+    if (first + n < first) return fail(c, MC_E_INVALID_ARG, "photon range wraps");
+    rc = refresh_tables(c);
+    if (rc) return rc;
+    rc = check_overflow(c, first + n);
+    if (rc) return rc;
+    common_params(c, p);
+    p.G = grid_of(c, ph);
+    p.F = frame_of(c->g, beta);
     p.first = first;
     p.n = n;
     p.key0 = (uint32_t)seed;
     p.key1 = (uint32_t)(seed >> 32);
-    p.steps_per_round = c->steps_per_round > 0 ? c->steps_per_round : 64;
     p.counter = c->d_ctl + (c->launches++ % kRing);
-    p.stats = c->d_ctl + kRing;
     return MC_OK;
 }
 
-void launch_shape(mc_ctx *c, uint64_t n, bool stats, int &grid, int &block) {
+void launch_shape(mc_ctx *c, const KParams &p, int layout, bool stats, int &grid, int &block) {
     block = c->block > 0 ? c->block : 256;
-    int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
-                                   : transport_blocks_per_cu(block, (int)c->mats.size(), stats);
-    uint64_t full = (uint64_t)bpc * c->n_cu;
-    uint64_t need = (n + block - 1) / block;
+    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
+                                         : transport_blocks_per_cu(p, layout, block, stats);
+    const uint64_t full = (uint64_t)bpc * c->n_cu;
+    const uint64_t need = (p.n + block - 1) / block;
     grid = (int)std::max<uint64_t>(1, std::min(full, need));
 }
 
 mc_status run(mc_ctx *c, KParams &p, hipStream_t s, bool debug) {
     if (p.n == 0) return MC_OK;
     HIP_TRY(c, hipMemsetAsync(p.counter, 0, sizeof(unsigned long long), s));
+    const bool stats = c->stats_on && !debug;
+    const int layout = p.G.layout;
     int grid, block;
-    launch_shape(c, p.n, c->stats_on && !debug, grid, block);
-    if (!c->stats_on || debug) p.stats = nullptr;
-    hipError_t e = launch_transport(p, grid, block, c->stats_on && !debug, debug, s);
+    launch_shape(c, p, layout, stats, grid, block);
+    if (!stats) p.stats = nullptr;
+    hipError_t e = launch_transport(p, layout, grid, block, stats, debug, s);
     if (e != hipSuccess) return hip_fail(c, e, "transport launch");
     return MC_OK;
 }
@@ -314,8 +410,10 @@ void mc_destroy(mc_ctx *c) {
     }
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    if (c->d_ids) (void)hipFree(c->d_ids);
-    if (c->d_rho) (void)hipFree(c->d_rho);
+    for (Phantom &ph : c->phantoms) ph.release();
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->d_batch) (void)hipFree(c->d_batch);
     if (c->d_tables) (void)hipFree(c->d_tables);
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->d_img) (void)hipFree(c->d_img);
@@ -336,36 +434,160 @@ mc_status mc_set_materials(mc_ctx *c, const mc_material *m, int n) {
     return MC_OK;
 }
 
-mc_status mc_load_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny,
-                          int nz, float h) {
-    if (!c) return MC_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Validate a voxel object, build its bricked device representation into `out`
+// (replacing what `out` held).
+mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny, int nz,
+                        float h, Phantom &out) {
     if (!ids || !rho || nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096 ||
         !(h > 0.0f) || !std::isfinite(h))
         return fail(c, MC_E_INVALID_ARG, "bad phantom dimensions");
+    const int nbx = (nx + kBx - 1) / kBx, nby = (ny + kBy - 1) / kBy, nbz = (nz + kBz - 1) / kBz;
     const size_t nv = (size_t)nx * ny * nz;
-    if (nv >= (size_t)1 << 31) return fail(c, MC_E_INVALID_ARG, "phantom must have < 2^31 voxels");
+    const size_t padded = (size_t)nbx * nby * nbz * kBrick;
+    if (padded >= (size_t)1 << 31) return fail(c, MC_E_INVALID_ARG, "phantom too large (2^31 voxels)");
+    // validate and collect the distinct (id, density) pairs, first appearance first
     int max_id = 0;
+    uint32_t pal_rho_bits[256];
+    uint8_t pal_id[256];
+    int n_pal = 0;
+    bool palette_ok = c->layout_req != MC_LAYOUT_GENERIC;
+    uint64_t table[1024] = {0};
+    int16_t slot_pal[1024];
+    std::memset(slot_pal, 0xff, sizeof slot_pal);
+    uint64_t last_key = ~0ull;
     for (size_t i = 0; i < nv; ++i) {
         const float r = rho[i];
         if (!std::isfinite(r) || r < 0.0f || r > 1000.0f)
             return fail(c, MC_E_INVALID_ARG, "density at %zu must be finite and in [0, 1000]", i);
         max_id = std::max<int>(max_id, ids[i]);
+        if (!palette_ok) continue;
+        uint32_t bits;
+        std::memcpy(&bits, &r, 4);
+        const uint64_t key = ((uint64_t)ids[i] << 32) | bits;
+        if (key == last_key) continue;
+        last_key = key;
+        uint32_t hsh = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);   // 10 bits
+        for (;;) {
+            if (slot_pal[hsh] < 0) {
+                if (n_pal == 256) {
+                    palette_ok = false;
+                    break;
+                }
+                slot_pal[hsh] = (int16_t)n_pal;
+                table[hsh] = key;
+                pal_id[n_pal] = ids[i];
+                pal_rho_bits[n_pal] = bits;
+                ++n_pal;
+                break;
+            }
+            if (table[hsh] == key) break;
+            hsh = (hsh + 1) & 1023;
+        }
     }
+    if (c->layout_req != MC_LAYOUT_AUTO && c->layout_req != MC_LAYOUT_GENERIC && !palette_ok)
+        return fail(c, MC_E_INVALID_ARG, "palette layout requested but the object has > 256 "
+                                         "distinct (material, density) pairs");
     mc_status rc = use_device(c);
     if (rc) return rc;
+    // bricked host images
+    std::vector<uint8_t> vox(padded, 0);
+    std::vector<float> vr;
+    if (!palette_ok) vr.assign(padded, 0.0f);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const size_t row = ((size_t)z * ny + y) * nx;
+            const size_t bzy = ((size_t)(z / kBz) * nby + (y / kBy)) * nbx;
+            const int inner = ((z % kBz) * kBy + (y % kBy)) * kBx;
+            uint64_t last = ~0ull;
+            uint8_t last_code = 0;
+            for (int x = 0; x < nx; ++x) {
+                const size_t off = (bzy + x / kBx) * kBrick + inner + (x % kBx);
+                if (!palette_ok) {
+                    vox[off] = ids[row + x];
+                    vr[off] = rho[row + x];
+                    continue;
+                }
+                uint32_t bits;
+                std::memcpy(&bits, &rho[row + x], 4);
+                const uint64_t key = ((uint64_t)ids[row + x] << 32) | bits;
+                if (key != last) {
+                    uint32_t hsh = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);
+                    while (slot_pal[hsh] < 0 || table[hsh] != key) hsh = (hsh + 1) & 1023;
+                    last = key;
+                    last_code = (uint8_t)slot_pal[hsh];
+                }
+                vox[off] = last_code;
+            }
+        }
     HIP_TRY(c, hipDeviceSynchronize());
-    if (c->d_ids) (void)hipFree(c->d_ids);
-    if (c->d_rho) (void)hipFree(c->d_rho);
-    c->d_ids = nullptr;
-    c->d_rho = nullptr;
-    c->have_phantom = false;
-    HIP_TRY(c, hipMalloc(&c->d_ids, nv));
-    HIP_TRY(c, hipMalloc(&c->d_rho, nv * sizeof(float)));
-    HIP_TRY(c, hipMemcpy(c->d_ids, ids, nv, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_rho, rho, nv * sizeof(float), hipMemcpyHostToDevice));
-    c->nx = nx; c->ny = ny; c->nz = nz; c->h = h;
-    c->max_id = max_id;
-    c->have_phantom = true;
+    out.release();
+    HIP_TRY(c, hipMalloc(&out.d_vox, padded));
+    HIP_TRY(c, hipMemcpy(out.d_vox, vox.data(), padded, hipMemcpyHostToDevice));
+    if (!palette_ok) {
+        HIP_TRY(c, hipMalloc(&out.d_vrho, padded * sizeof(float)));
+        HIP_TRY(c, hipMemcpy(out.d_vrho, vr.data(), padded * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        unsigned char pal[256 * 5] = {0};
+        std::memcpy(pal, pal_rho_bits, (size_t)n_pal * 4);
+        std::memcpy(pal + 256 * 4, pal_id, (size_t)n_pal);
+        HIP_TRY(c, hipMalloc(&out.d_pal, sizeof pal));
+        HIP_TRY(c, hipMemcpy(out.d_pal, pal, sizeof pal, hipMemcpyHostToDevice));
+    }
+    out.nx = nx; out.ny = ny; out.nz = nz; out.h = h;
+    out.nbx = nbx; out.nby = nby; out.nbz = nbz;
+    out.max_id = max_id;
+    out.generic = !palette_ok;
+    out.n_pal = palette_ok ? n_pal : 0;
+    out.loaded = true;
+    ++c->generation;
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_status mc_load_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny,
+                          int nz, float h) {
+    if (!c) return MC_E_INVALID_ARG;
+    const mc_status rc = build_phantom(c, ids, rho, nx, ny, nz, h, c->phantoms[0]);
+    c->have_phantom = c->phantoms[0].loaded;
+    return rc;
+}
+
+mc_status mc_phantom_add(mc_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny,
+                         int nz, float h, int *handle) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!handle) return fail(c, MC_E_INVALID_ARG, "null handle");
+    if (c->phantoms.size() >= 4096) return fail(c, MC_E_INVALID_ARG, "too many phantoms");
+    Phantom ph;
+    mc_status rc = build_phantom(c, ids, rho, nx, ny, nz, h, ph);
+    if (rc) return rc;
+    c->phantoms.push_back(ph);
+    *handle = (int)c->phantoms.size() - 1;
+    return MC_OK;
+}
+
+mc_status mc_set_layout(mc_ctx *c, int layout) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (layout < MC_LAYOUT_AUTO || layout > MC_LAYOUT_GENERIC)
+        return fail(c, MC_E_INVALID_ARG, "unknown layout %d", layout);
+    c->layout_req = layout;
+    return MC_OK;
+}
+
+mc_status mc_get_layout(mc_ctx *c, int *layout, int *palette_size) {
+    if (!c || !layout || !palette_size) return MC_E_INVALID_ARG;
+    if (!c->have_phantom) return fail(c, MC_E_STATE, "no phantom loaded");
+    const Phantom &ph = c->phantoms[0];
+    const int l = phantom_layout(c, ph);
+    *layout = l == kGeneric ? MC_LAYOUT_GENERIC
+              : l == kPaletteShared ? MC_LAYOUT_PALETTE_SHARED : MC_LAYOUT_PALETTE_LANE;
+    *palette_size = ph.n_pal;
     return MC_OK;
 }
 
@@ -384,6 +606,7 @@ mc_status mc_set_geometry(mc_ctx *c, const mc_geometry *g) {
     if (g->flags & ~MC_NO_SCATTER) return fail(c, MC_E_INVALID_ARG, "unknown flags");
     c->g = *g;
     c->have_geom = true;
+    ++c->generation;
     return MC_OK;
 }
 
@@ -477,6 +700,127 @@ mc_status mc_project(mc_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *
     return MC_OK;
 }
 
+mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                           uint64_t out_elems, uint32_t flags, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!jobs || n_jobs < 1 || n_jobs > 65536 || !d_out)
+        return fail(c, MC_E_INVALID_ARG, "need 1..65536 jobs and an output buffer");
+    if (flags & ~MC_BATCH_GRAPH) return fail(c, MC_E_INVALID_ARG, "unknown batch flags");
+    if (!c->have_geom || !c->have_spec) return fail(c, MC_E_STATE, "geometry and spectrum must be set");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    const uint64_t np = (uint64_t)c->g.nu * c->g.nv, ns = (uint64_t)c->g.snu * c->g.snv;
+    uint64_t n_max = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const mc_job &jb = jobs[j];
+        if (jb.phantom < 0 || jb.phantom >= (int)c->phantoms.size() || !c->phantoms[jb.phantom].loaded)
+            return fail(c, MC_E_INVALID_ARG, "job %d: unknown phantom %d", j, jb.phantom);
+        if (!std::isfinite(jb.angle_rad)) return fail(c, MC_E_INVALID_ARG, "job %d: bad angle", j);
+        if (jb.primary_offset > out_elems || out_elems - jb.primary_offset < np ||
+            jb.scatter_offset > out_elems || out_elems - jb.scatter_offset < ns)
+            return fail(c, MC_E_INVALID_ARG, "job %d: images outside the output buffer", j);
+        rc = check_phantom(c, c->phantoms[jb.phantom]);
+        if (rc) return rc;
+        n_max = std::max(n_max, jb.n_photons);
+    }
+    rc = refresh_tables(c);
+    if (rc) return rc;
+    rc = check_overflow(c, n_max);
+    if (rc) return rc;
+
+    // device tables: grids for every phantom, then jobs, then per-job counters
+    const int n_grid = (int)c->phantoms.size();
+    const size_t gb = ((n_grid * sizeof(VoxelGrid) + 255) / 256) * 256;
+    const size_t jbytes = ((n_jobs * sizeof(JobDesc) + 255) / 256) * 256;
+    const size_t bytes = gb + jbytes + (size_t)n_jobs * 8;
+    hipStream_t s = (hipStream_t)stream;
+    if (bytes > c->d_batch_bytes) {
+        HIP_TRY(c, hipDeviceSynchronize());
+        if (c->d_batch) (void)hipFree(c->d_batch);
+        c->d_batch = nullptr;
+        c->d_batch_bytes = 0;
+        HIP_TRY(c, hipMalloc(&c->d_batch, bytes));
+        c->d_batch_bytes = bytes;
+        ++c->generation;
+    }
+    std::vector<unsigned char> host(gb + jbytes, 0);
+    VoxelGrid *hg = (VoxelGrid *)host.data();
+    int max_lane_pal = 0;
+    for (int i = 0; i < n_grid; ++i) {
+        if (!c->phantoms[i].loaded) continue;
+        hg[i] = grid_of(c, c->phantoms[i]);
+        if (hg[i].layout == kPaletteLane) max_lane_pal = std::max(max_lane_pal, hg[i].n_pal);
+    }
+    JobDesc *hj = (JobDesc *)(host.data() + gb);
+    for (int j = 0; j < n_jobs; ++j) {
+        const mc_job &jb = jobs[j];
+        hj[j].F = frame_of(c->g, jb.angle_rad);
+        hj[j].key0 = (uint32_t)jb.seed;
+        hj[j].key1 = (uint32_t)(jb.seed >> 32);
+        hj[j].n = jb.n_photons;
+        hj[j].prim = (unsigned long long *)(d_out + jb.primary_offset);
+        hj[j].scat = (unsigned long long *)(d_out + jb.scatter_offset);
+        hj[j].grid = jb.phantom;
+    }
+    unsigned char *db = (unsigned char *)c->d_batch;
+    HIP_TRY(c, hipMemcpyAsync(db, host.data(), gb + jbytes, hipMemcpyHostToDevice, s));
+
+    KParams p;
+    common_params(c, p);
+    p.grids = (const VoxelGrid *)db;
+    p.jobs = (const JobDesc *)(db + gb);
+    p.job_counters = (unsigned long long *)(db + gb + jbytes);
+    p.n_jobs = n_jobs;
+    p.F = hj[0].F;
+    const bool stats = c->stats_on;
+    if (!stats) p.stats = nullptr;
+    const int block = c->block > 0 ? c->block : 256;
+    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
+                                         : batch_blocks_per_cu(p, max_lane_pal, block, stats);
+    uint64_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) total += jobs[j].n_photons;
+    const int grid = (int)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, (total + block - 1) / block));
+
+    if (!(flags & MC_BATCH_GRAPH)) {
+        hipError_t e = launch_clear((unsigned long long *)d_out, out_elems, p.job_counters,
+                                    (size_t)n_jobs, s);
+        if (e == hipSuccess) e = launch_batch(p, max_lane_pal, grid, block, stats, s);
+        if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+        return MC_OK;
+    }
+    // graph: clear kernel -> persistent transport kernel, captured once per
+    // (buffers, shape, state) and replayed; the job table is uploaded above
+    std::vector<unsigned char> key(sizeof(KParams) + 4 * sizeof(uint64_t));
+    std::memcpy(key.data(), &p, sizeof p);
+    const uint64_t extra[4] = {out_elems, (uint64_t)grid, (uint64_t)block,
+                               ((uint64_t)c->generation << 8) | (uint64_t)max_lane_pal};
+    std::memcpy(key.data() + sizeof p, extra, sizeof extra);
+    if (!c->graph_exec || key != c->graph_key) {
+        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+        c->graph_key.clear();
+        HIP_TRY(c, hipStreamSynchronize(s));
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_clear((unsigned long long *)d_out, out_elems, p.job_counters,
+                                    (size_t)n_jobs, c->stream);
+        if (e == hipSuccess) e = launch_batch(p, max_lane_pal, grid, block, stats, c->stream);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return hip_fail(c, e != hipSuccess ? e : e2, "batch graph capture");
+        }
+        c->graph = gr;
+        HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0));
+        c->graph_key = key;
+    }
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+    return MC_OK;
+}
+
 mc_status mc_debug_histories(mc_ctx *c, float beta, uint64_t first, uint64_t m, uint64_t seed,
                              uint16_t *n_int, uint32_t *steps, uint8_t *end, uint8_t *first_t) {
     if (!c) return MC_E_INVALID_ARG;
@@ -535,6 +879,7 @@ mc_status mc_test_sample(mc_ctx *c, int process, int material, float e_kev, uint
         if (rc) return rc;
         p.e_bin = c->dp_ebin;
         p.thr = c->dp_thr;
+        p.guide = c->dp_guide;
         p.n_bins = (int)c->e_bin.size();
     } else if (process == MC_PROC_SOURCE_DIR) {
         if (!cos_out) return fail(c, MC_E_INVALID_ARG, "null output");
@@ -610,15 +955,15 @@ mc_status mc_get_tables(mc_ctx *c, int *J, float *pe, float *coh, float *inc, fl
     return MC_OK;
 }
 
-mc_status mc_set_launch(mc_ctx *c, int block, int blocks_per_cu, int steps_per_round) {
+mc_status mc_set_launch(mc_ctx *c, int block, int blocks_per_cu, int event_batch) {
     if (!c) return MC_E_INVALID_ARG;
     if (block != 0 && (block < 64 || block > 256 || block % 64))
         return fail(c, MC_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
-    if (blocks_per_cu < 0 || blocks_per_cu > 64 || steps_per_round < 0 || steps_per_round > 4096)
+    if (blocks_per_cu < 0 || blocks_per_cu > 64 || event_batch < 0 || event_batch > 64)
         return fail(c, MC_E_INVALID_ARG, "bad launch shape");
     c->block = block;
     c->blocks_per_cu = blocks_per_cu;
-    c->steps_per_round = steps_per_round;
+    c->event_batch = event_batch;
     return MC_OK;
 }
 

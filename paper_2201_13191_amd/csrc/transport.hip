@@ -6,11 +6,12 @@
 // Execution model: a persistent grid.  Each lane carries one photon; a wave
 // refills its dead lanes from a global photon counter with one atomic per
 // wave (ballot + popcount + prefix count), so lanes never wait for the
-// wave's longest history.  Each scheduling round (1) starts flights for
-// lanes that need one, (2) marches every flying lane up to
-// `steps_per_round` fixed steps, (3) handles the lanes whose flight ended:
-// an interaction (type draw, angle sampling, rotation) or an exit (panel
-// crossing and tally).
+// wave's longest history.  Each scheduling round handles, together, every
+// lane waiting for an event -- interactions (type draw, angle sampling in
+// fp64, rotation), panel crossings (int64 tally), refills and births, new
+// flights -- and then marches all flying lanes until `event_batch` lanes are
+// waiting again.  Batching keeps the expensive event code from running for
+// one or two lanes at a time.
 //
 // Reproducibility: every photon owns a Philox4x32-10 stream (key = seed,
 // counter = photon id, draw index / 4), all fp32 state is updated with
@@ -156,17 +157,16 @@ __device__ __forceinline__ void scatter_direction(float &dx, float &dy, float &d
     dz = nz * inv;
 }
 
+// first bin k with x < thr[k]: the guide table gives the first candidate of
+// x's top-byte bucket, a short scan finds the bin (thr[n_bins-1] = 2^32)
 __device__ __forceinline__ uint32_t pick_bin(const KParams &p, uint32_t x) {
-    int lo = 0, hi = p.n_bins - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((uint64_t)x < p.thr[mid]) hi = mid; else lo = mid + 1;
-    }
-    return (uint32_t)lo;
+    uint32_t k = p.guide[x >> 24];
+    while ((uint64_t)x >= p.thr[k]) ++k;
+    return k;
 }
 
 // ------------------------------------------------------------------ geometry
-__device__ __forceinline__ bool box_entry(const KParams &p, const float o[3], const float d[3],
+__device__ __forceinline__ bool box_entry(const VoxelGrid &p, const float o[3], const float d[3],
                                           float &tin, float &tout) {
     float t0 = 0.0f, t1 = __builtin_inff();
 #pragma unroll
@@ -188,9 +188,8 @@ __device__ __forceinline__ bool box_entry(const KParams &p, const float o[3], co
     return t0 < t1;
 }
 
-__device__ __forceinline__ bool panel_hit(const KParams &p, const float o[3], const float d[3],
-                                          int &iu, int &iv) {
-    const ProjFrame &F = p.F;
+__device__ __forceinline__ bool panel_hit(const KParams &p, const ProjFrame &F, const float o[3],
+                                          const float d[3], int &iu, int &iv) {
     const float den = (d[0] * F.ax[0] + d[1] * F.ax[1]) + d[2] * F.ax[2];
     if (!(den > 0.0f)) return false;
     const float rel = ((o[0] - F.S[0]) * F.ax[0] + (o[1] - F.S[1]) * F.ax[1]) +
@@ -213,136 +212,120 @@ __device__ __forceinline__ bool panel_hit(const KParams &p, const float o[3], co
 enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim, kStScat,
              kStCut, kStCap, kStCount };
 
+#ifndef MCX_PREFETCH
+#define MCX_PREFETCH 4
+#endif
+constexpr int kPrefetch = MCX_PREFETCH;   // march steps whose voxel loads are issued together
+constexpr int kLdsHeader = 256 + 64;   // floats: palette densities, then 256 palette ids
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-template <bool STATS, bool DEBUG>
+// byte offset of voxel (ix, iy, iz) in the bricked arrays: brick slab and
+// row strides times brick indices (24-bit multiplies; brick indices are
+// below 2^10), plus the brick column and the position inside the brick
+__device__ __forceinline__ uint32_t brick_offset(const VoxelGrid &p, uint32_t ix, uint32_t iy,
+                                                 uint32_t iz) {
+    const uint32_t b = __umul24(iz >> 2, p.sz) + __umul24(iy >> 2, p.sy) + ((ix >> 3) << 7);
+    return b | ((iz & 3u) << 5) | ((iy & 3u) << 3) | (ix & 7u);
+}
+
+// voxel index along one axis: truncation of the voxel coordinate clamped to
+// [0, n - 1]; clamping the float first is the same as clamping the integer
+// and needs one median instruction
+__device__ __forceinline__ uint32_t voxel_index(float c, float cmax) {
+    return (uint32_t)__builtin_amdgcn_fmed3f(c, 0.0f, cmax);
+}
+
+// MODE: layout of the single object (ignored for batches, where each lane
+// follows the layout of its own job's object).  BATCH: run the job table.
+template <int MODE, bool BATCH, bool STATS, bool DEBUG>
 __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
-    extern __shared__ float lds_mu[];        // [n_mat][blockDim]: lane-private columns
+    // LDS: palette densities [256] | palette ids [256 bytes] (single object only) |
+    // lane-private columns: mu per material [n_mat][bs], then mu per palette
+    // entry [n_pal][bs] for per-lane palette tables
+    extern __shared__ float lds[];
+    float *s_pal_rho = lds;
+    uint8_t *s_pal_id = (uint8_t *)(lds + 256);
     const int bs = blockDim.x;
-    float *mm = lds_mu + threadIdx.x;
+    float *mm = lds + kLdsHeader + threadIdx.x;
+    float *mu_pal = mm + p.n_mat * bs;
     const int lane = (int)__lane_id();
+    if (!BATCH && MODE != kGeneric) {
+        for (int i = threadIdx.x; i < p.G.n_pal; i += bs) {
+            s_pal_rho[i] = p.G.pal_rho[i];
+            s_pal_id[i] = p.G.pal_id[i];
+        }
+        __syncthreads();
+    }
+
+    // the lane's voxel object (uniform for a single projection)
+    VoxelGrid gl = p.G;
+    int job = 0;          // batch: the lane's job
+    int cur_job = 0;      // batch: the job this wave refills from
+    auto frame = [&]() -> const ProjFrame & { return BATCH ? p.jobs[job].F : p.F; };
 
     bool alive = false, flying = false, exhausted = false;
     PhotonStream rng;
     uint64_t pid = 0;
     float e = 0.0f;
     float o[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
-    float pin[3], q[3], g[3];
-    float len = 0.0f, tau = 0.0f, tau_star = 0.0f;
+    float q[3], g[3];
+    float tin = 0.0f, len = 0.0f, tau = 0.0f, tau_star = 0.0f;
     uint32_t k = 0;
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
     uint8_t h_first = 0;
 
-    for (;;) {
-        // ---- refill dead lanes: one atomic per wave
-        if (!exhausted) {
-            const unsigned long long dead = __ballot(!alive);
-            if (dead) {
-                const unsigned nd = (unsigned)__popcll(dead);
-                const int leader = __ffsll(dead) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(p.counter, (unsigned long long)nd);
-                base = __shfl(base, leader);
-                if (base + nd >= p.n) exhausted = true;
-                if (!alive) {
-                    const unsigned long long below = dead & ((1ull << lane) - 1ull);
-                    const unsigned long long idx = base + (unsigned long long)__popcll(below);
-                    if (idx < p.n) {
-                        pid = p.first + idx;
-                        rng.reset(pid, p.key0, p.key1);
-                        e = p.e_bin[pick_bin(p, rng.raw())];
-                        const float ct = 1.0f - rng.u() * p.F.omc;
-                        const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-                        double sphi, cphi;
-                        sincos(6.283185307179586 * (double)rng.u(), &sphi, &cphi);
-                        const float cp = (float)cphi, sp = (float)sphi;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            d[a] = (ct * p.F.ax[a] + (stt * cp) * p.F.eu[a]) +
-                                   (stt * sp) * p.F.ev[a];
-                            o[a] = p.F.S[a];
-                        }
-                        material_mu(p, e, mm, bs);
-                        n_int = 0;
-                        alive = true;
-                        flying = false;
-                        h_steps = 0;
-                        h_first = 0;
-                        if (STATS) ++st[kStHist];
-                    }
-                }
-            }
+    // attenuation at the photon's energy: per material, and per palette entry
+    auto refresh_mu = [&](float energy) {
+        material_mu(p, energy, mm, bs);
+        if (BATCH) {
+            if (gl.layout == kPaletteLane)
+                for (int c = 0; c < gl.n_pal; ++c)
+                    mu_pal[c * bs] = gl.pal_rho[c] * mm[gl.pal_id[c] * bs];
+        } else if (MODE == kPaletteLane) {
+            for (int c = 0; c < p.G.n_pal; ++c)
+                mu_pal[c * bs] = s_pal_rho[c] * mm[s_pal_id[c] * bs];
         }
-        if (!__any(alive)) break;
+    };
+    // a new photon: energy bin, direction in the cone, position at the source
+    auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1) {
+        pid = photon;
+        rng.reset(pid, k0, k1);
+        e = p.e_bin[pick_bin(p, rng.raw())];
+        const ProjFrame &F = frame();
+        const float ct = 1.0f - rng.u() * F.omc;
+        const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        double sphi, cphi;
+        sincos(6.283185307179586 * (double)rng.u(), &sphi, &cphi);
+        const float cp = (float)cphi, sp = (float)sphi;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            d[a] = (ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
+            o[a] = F.S[a];
+        }
+        refresh_mu(e);
+        n_int = 0;
+        alive = true;
+        flying = false;
+        if (DEBUG) {
+            h_steps = 0;
+            h_first = 0;
+        }
+        if (STATS) ++st[kStHist];
+    };
 
-        int event = 0;   // 1 interaction, 2 left the object or missed it
-        // ---- start flights
-        if (alive && !flying) {
-            float tin, tout;
-            if (box_entry(p, o, d, tin, tout)) {
-                tau_star = (float)(-log((double)rng.u()));
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    pin[a] = o[a] + d[a] * tin;
-                    q[a] = (pin[a] - p.lo[a]) * p.inv_h;
-                    g[a] = d[a] * p.inv_h;
-                }
-                len = tout - tin;
-                tau = 0.0f;
-                k = 0;
-                flying = true;
-                if (STATS) ++st[kStFlights];
-            } else {
-                event = 2;
-            }
-        }
-        // ---- march
-        if (flying) {
-            for (int it = 0; it < p.steps_per_round; ++it) {
-                const float a0 = (float)k * p.step;
-                if (!(a0 < len)) {
-                    event = 2;
-                    break;
-                }
-                float b = a0 + p.step;
-                if (b > len) b = len;
-                const float dk = b - a0;
-                const float s = 0.5f * (a0 + b);
-                int ix = (int)(q[0] + g[0] * s);
-                int iy = (int)(q[1] + g[1] * s);
-                int iz = (int)(q[2] + g[2] * s);
-                ix = min(max(ix, 0), p.nx - 1);
-                iy = min(max(iy, 0), p.ny - 1);
-                iz = min(max(iz, 0), p.nz - 1);
-                const int v = (iz * p.ny + iy) * p.nx + ix;
-                const int id = p.ids[v];
-                const float mu = p.rho[v] * mm[id * bs];
-                const float x = mu * dk;
-                const float tn = tau + x;
-                if (DEBUG) ++h_steps;
-                if (STATS) ++st[kStSteps];
-                if (tn >= tau_star) {
-                    const float si = a0 + (tau_star - tau) / mu;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) o[a] = pin[a] + d[a] * si;
-                    mat = id;
-                    event = 1;
-                    break;
-                }
-                tau = tn;
-                ++k;
-            }
-        }
-        if (event) flying = false;
+    int event = 0;   // pending: 1 interaction, 2 reaches the panel plane (left or missed the box)
+    for (;;) {
         int end = -1;
-        // ---- interaction
+        // ---- 1. interactions of lanes whose flight ended inside the object
         if (event == 1) {
+            event = 0;
             const int off = mat * p.J;
             const float a = grid_lerp(p.pe + off, p.J, e);
             const float b = grid_lerp(p.coh + off, p.J, e);
@@ -377,22 +360,25 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     end = 5;
                 } else if (e2 != e) {
                     e = e2;
-                    material_mu(p, e, mm, bs);
+                    refresh_mu(e);
                 }
             }
         } else if (event == 2) {
-            // ---- panel
+            // ---- 2. panel crossings
+            event = 0;
             int iu, iv;
-            if (panel_hit(p, o, d, iu, iv)) {
+            if (panel_hit(p, frame(), o, d, iu, iv)) {
                 const float w = grid_lerp(p.eta, p.J, e);
                 const long long t = (long long)rintf(w * 1048576.0f);
+                unsigned long long *prim = BATCH ? p.jobs[job].prim : p.prim;
+                unsigned long long *scat = BATCH ? p.jobs[job].scat : p.scat;
                 if (n_int == 0) {
-                    atomicAdd(p.prim + (size_t)iv * p.nu + iu, (unsigned long long)t);
+                    atomicAdd(prim + (size_t)iv * p.nu + iu, (unsigned long long)t);
                     if (STATS) ++st[kStPrim];
                     end = 0;
                 } else {
                     const int su = iu / p.bu, sv = iv / p.bv;
-                    atomicAdd(p.scat + (size_t)sv * p.snu + su, (unsigned long long)t);
+                    atomicAdd(scat + (size_t)sv * p.snu + su, (unsigned long long)t);
                     if (STATS) ++st[kStScat];
                     end = 1;
                 }
@@ -409,6 +395,139 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 if (p.dbg_first) p.dbg_first[r] = h_first;
             }
             alive = false;
+        }
+        // ---- 3. refill dead lanes: one atomic per wave (per job touched)
+        if (!exhausted) {
+            unsigned long long dead = __ballot(!alive);
+            while (dead) {
+                const unsigned nd = (unsigned)__popcll(dead);
+                const int leader = __ffsll(dead) - 1;
+                unsigned long long *ctr = BATCH ? p.job_counters + cur_job : p.counter;
+                const unsigned long long total = BATCH ? p.jobs[cur_job].n : p.n;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(ctr, (unsigned long long)nd);
+                base = __shfl(base, leader);
+                const unsigned long long got =
+                    base < total ? (total - base < nd ? total - base : nd) : 0ull;
+                if (!alive) {
+                    const unsigned long long rank =
+                        (unsigned long long)__popcll(dead & ((1ull << lane) - 1ull));
+                    if (rank < got) {
+                        if (BATCH) {
+                            job = cur_job;
+                            gl = p.grids[p.jobs[job].grid];
+                            birth(base + rank, p.jobs[job].key0, p.jobs[job].key1);
+                        } else {
+                            birth(p.first + base + rank, p.key0, p.key1);
+                        }
+                    }
+                }
+                if (got == nd && base + nd < total) break;
+                // the current job has no photons left
+                if (BATCH && cur_job + 1 < p.n_jobs) {
+                    ++cur_job;
+                    dead = __ballot(!alive);
+                } else {
+                    exhausted = true;
+                    break;
+                }
+            }
+        }
+        if (!__any(alive)) break;
+
+        // ---- 4. start flights (new photons and scattered ones)
+        if (alive && !flying && event == 0) {
+            float tout;
+            if (box_entry(gl, o, d, tin, tout)) {
+                tau_star = (float)(-log((double)rng.u()));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float pin = o[a] + d[a] * tin;
+                    q[a] = (pin - gl.lo[a]) * gl.inv_h;
+                    g[a] = d[a] * gl.inv_h;
+                }
+                len = tout - tin;
+                tau = 0.0f;
+                k = 0;
+                flying = true;
+                if (STATS) ++st[kStFlights];
+            } else {
+                event = 2;
+            }
+        }
+        // ---- 5. march until `event_batch` lanes wait for an event (or none flies).
+        //         Each group issues the voxel loads of kPrefetch consecutive steps,
+        //         then consumes them in order without branches: tau and the step
+        //         index advance by selection, the step that reaches tau* is recorded,
+        //         and the interaction point is computed once after the group.
+        for (;;) {
+            if (!__any(flying)) break;
+            if (__popcll(__ballot(alive && !flying)) >= (unsigned)p.event_batch) break;
+            if (!flying) continue;
+            uint32_t code[kPrefetch];
+            float vr[kPrefetch], a0v[kPrefetch], dkv[kPrefetch];
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const float a0 = (float)(k + u) * p.step;
+                float b = a0 + p.step;
+                if (b > len) b = len;
+                a0v[u] = a0;
+                dkv[u] = b - a0;
+                const float s = 0.5f * (a0 + b);
+                const uint32_t ix = voxel_index(q[0] + g[0] * s, gl.cmax[0]);
+                const uint32_t iy = voxel_index(q[1] + g[1] * s, gl.cmax[1]);
+                const uint32_t iz = voxel_index(q[2] + g[2] * s, gl.cmax[2]);
+                const uint32_t off = brick_offset(gl, ix, iy, iz);
+                code[u] = gl.vox[off];
+                if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+            }
+            const int lay = BATCH ? gl.layout : MODE;
+            bool act = true, hit = false, out = false;
+            float mu_hit = 1.0f;
+            uint32_t code_hit = 0;
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                float mu;
+                if (lay == kPaletteLane)
+                    mu = mu_pal[code[u] * bs];
+                else if (lay == kPaletteShared)
+                    mu = BATCH ? gl.pal_rho[code[u]] * mm[gl.pal_id[code[u]] * bs]
+                               : s_pal_rho[code[u]] * mm[s_pal_id[code[u]] * bs];
+                else
+                    mu = vr[u] * mm[code[u] * bs];
+                const bool inside = a0v[u] < len;
+                const float tn = tau + mu * dkv[u];
+                const bool step = act && inside;
+                const bool reach = step && (tn >= tau_star);
+                if (DEBUG) h_steps += step ? 1u : 0u;
+                if (STATS) st[kStSteps] += step ? 1ull : 0ull;
+                out = out || (act && !inside);
+                hit = hit || reach;
+                mu_hit = reach ? mu : mu_hit;
+                code_hit = reach ? code[u] : code_hit;
+                const bool adv = step && !reach;
+                tau = adv ? tn : tau;
+                k += adv ? 1u : 0u;
+                act = adv;
+            }
+            if (hit) {
+                const float a0 = (float)k * p.step;
+                const float si = a0 + (tau_star - tau) / mu_hit;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float pin = o[a] + d[a] * tin;
+                    o[a] = pin + d[a] * si;
+                }
+                if (lay == kGeneric)
+                    mat = (int)code_hit;
+                else
+                    mat = BATCH ? (int)gl.pal_id[code_hit] : (int)s_pal_id[code_hit];
+                event = 1;
+                flying = false;
+            } else if (out) {
+                event = 2;
+                flying = false;
+            }
         }
     }
     if (STATS) {
@@ -442,18 +561,68 @@ __global__ void sample_kernel(const KParams p, int process, int material, float 
     }
 }
 
-hipError_t launch_transport(const KParams &p, int grid, int block, bool stats, bool debug,
-                            hipStream_t stream) {
-    const size_t lds = (size_t)p.n_mat * block * sizeof(float);
+size_t transport_lds_bytes(const KParams &p, int layout, int block) {
+    const int cols = p.n_mat + (layout == kPaletteLane ? p.G.n_pal : 0);
+    return (size_t)(kLdsHeader + cols * block) * sizeof(float);
+}
+
+// batches keep a per-lane palette table as large as the largest per-lane palette
+size_t batch_lds_bytes(const KParams &p, int max_lane_palette, int block) {
+    return (size_t)(kLdsHeader + (p.n_mat + max_lane_palette) * block) * sizeof(float);
+}
+
+template <int MODE>
+static hipError_t launch_mode(const KParams &p, int grid, int block, bool stats, bool debug,
+                              hipStream_t stream) {
+    const size_t lds = transport_lds_bytes(p, MODE, block);
     if (debug)
-        hipLaunchKernelGGL((transport_kernel<false, true>), dim3(grid), dim3(block), lds, stream,
-                           p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, false, true>), dim3(grid), dim3(block),
+                           lds, stream, p);
     else if (stats)
-        hipLaunchKernelGGL((transport_kernel<true, false>), dim3(grid), dim3(block), lds, stream,
-                           p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false>), dim3(grid), dim3(block),
+                           lds, stream, p);
     else
-        hipLaunchKernelGGL((transport_kernel<false, false>), dim3(grid), dim3(block), lds, stream,
-                           p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false>), dim3(grid), dim3(block),
+                           lds, stream, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(const KParams &p, int layout, int grid, int block, bool stats,
+                            bool debug, hipStream_t stream) {
+    if (layout == kPaletteLane) return launch_mode<kPaletteLane>(p, grid, block, stats, debug, stream);
+    if (layout == kPaletteShared)
+        return launch_mode<kPaletteShared>(p, grid, block, stats, debug, stream);
+    return launch_mode<kGeneric>(p, grid, block, stats, debug, stream);
+}
+
+hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int block, bool stats,
+                        hipStream_t stream) {
+    const size_t lds = batch_lds_bytes(p, max_lane_palette, block);
+    if (stats)
+        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, true, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
+    else
+        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, false, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
+    return hipGetLastError();
+}
+
+// zero a batch's images and counters: a plain fill kernel, so the batch can
+// be captured in a graph without memset nodes
+__global__ void clear_kernel(unsigned long long *a, size_t na, unsigned long long *b, size_t nb) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) a[i] = 0ull;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) b[i] = 0ull;
+}
+
+hipError_t launch_clear(unsigned long long *a, size_t na, unsigned long long *b, size_t nb,
+                        hipStream_t stream) {
+    const size_t n = na > nb ? na : nb;
+    const int block = 256;
+    size_t grid = (n + block - 1) / block;
+    if (grid > 4096) grid = 4096;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)grid), dim3(block), 0, stream, a, na, b, nb);
     return hipGetLastError();
 }
 
@@ -466,15 +635,29 @@ hipError_t launch_sample(const KParams &p, int process, int material, float e_ke
     return hipGetLastError();
 }
 
-int transport_blocks_per_cu(int block, int n_mat, bool stats) {
+template <int MODE, bool BATCH>
+static int occupancy(int block, size_t lds, bool stats) {
     int nb = 0;
-    const size_t lds = (size_t)n_mat * block * sizeof(float);
     if (stats)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true, false>,
-                                                           block, lds);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, transport_kernel<MODE, BATCH, true, false>, block, lds);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false, false>,
-                                                           block, lds);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, transport_kernel<MODE, BATCH, false, false>, block, lds);
+    return nb;
+}
+
+int transport_blocks_per_cu(const KParams &p, int layout, int block, bool stats) {
+    const size_t lds = transport_lds_bytes(p, layout, block);
+    int nb = layout == kPaletteLane     ? occupancy<kPaletteLane, false>(block, lds, stats)
+             : layout == kPaletteShared ? occupancy<kPaletteShared, false>(block, lds, stats)
+                                        : occupancy<kGeneric, false>(block, lds, stats);
+    return nb > 0 ? nb : 1;
+}
+
+int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats) {
+    const int nb = occupancy<kPaletteLane, true>(block, batch_lds_bytes(p, max_lane_palette, block),
+                                                stats);
     return nb > 0 ? nb : 1;
 }
 

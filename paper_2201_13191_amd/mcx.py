@@ -25,7 +25,10 @@ MC_END_PRIMARY, MC_END_SCATTER, MC_END_MISSED, MC_END_PHOTO, MC_END_CUTOFF, MC_E
 EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_load_phantom",
            "mc_set_geometry", "mc_set_spectrum", "mc_set_detector_response", "mc_project",
            "mc_project_async", "mc_project_range_async", "mc_debug_histories", "mc_test_sample",
-           "mc_set_stats", "mc_get_stats", "mc_get_tables", "mc_set_launch", "mc_tally_scale"]
+           "mc_set_stats", "mc_get_stats", "mc_get_tables", "mc_set_layout", "mc_get_layout",
+           "mc_set_launch", "mc_tally_scale", "mc_phantom_add", "mc_project_batch"]
+MC_BATCH_GRAPH = 1
+MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
 
 class mc_material(C.Structure):
@@ -39,6 +42,12 @@ class mc_geometry(C.Structure):
                 ("pu_mm", C.c_float), ("pv_mm", C.c_float),
                 ("snu", C.c_int32), ("snv", C.c_int32),
                 ("step_mm", C.c_float), ("flags", C.c_uint32)]
+
+
+class mc_job(C.Structure):
+    _fields_ = [("phantom", C.c_int32), ("angle_rad", C.c_float), ("n_photons", C.c_uint64),
+                ("seed", C.c_uint64), ("primary_offset", C.c_uint64),
+                ("scatter_offset", C.c_uint64)]
 
 
 class mc_stats(C.Structure):
@@ -82,8 +91,12 @@ def load():
         "mc_set_stats": ([P, I], I),
         "mc_get_stats": ([P, C.POINTER(mc_stats)], I),
         "mc_get_tables": ([P, C.POINTER(I), P, P, P, P], I),
+        "mc_set_layout": ([P, I], I),
+        "mc_get_layout": ([P, C.POINTER(I), C.POINTER(I)], I),
         "mc_set_launch": ([P, I, I, I], I),
         "mc_tally_scale": ([], C.c_double),
+        "mc_phantom_add": ([P, P, P, I, I, I, F, C.POINTER(I)], I),
+        "mc_project_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_uint32, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -147,6 +160,27 @@ def mc_load_phantom(ctx, ids, rho, voxel_mm):
     rho = np.ascontiguousarray(rho, dtype=np.float32)
     nz, ny, nx = ids.shape
     _check(ctx, load().mc_load_phantom(ctx, _np(ids), _np(rho), nx, ny, nz, float(voxel_mm)))
+
+
+def mc_phantom_add(ctx, ids, rho, voxel_mm):
+    ids = np.ascontiguousarray(ids, dtype=np.uint8)
+    rho = np.ascontiguousarray(rho, dtype=np.float32)
+    nz, ny, nx = ids.shape
+    h = C.c_int()
+    _check(ctx, load().mc_phantom_add(ctx, _np(ids), _np(rho), nx, ny, nz, float(voxel_mm),
+                                      C.byref(h)))
+    return h.value
+
+
+def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=None):
+    """jobs: sequence of dicts with phantom, angle_rad, n_photons, seed,
+    primary_offset, scatter_offset; d_out: device int64 buffer (torch tensor)."""
+    arr = (mc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = mc_job(j["phantom"], j["angle_rad"], j["n_photons"], j["seed"],
+                        j["primary_offset"], j["scatter_offset"])
+    _check(ctx, load().mc_project_batch(ctx, arr, len(jobs), _dev(d_out), out_elems, flags,
+                                        _stream(stream)))
 
 
 def mc_set_geometry(ctx, sod_mm, sdd_mm, nu, nv, pu_mm, pv_mm, step_mm, snu=None, snv=None,
@@ -222,8 +256,18 @@ def mc_get_tables(ctx, n_mat):
     return pe, coh, inc, eta
 
 
-def mc_set_launch(ctx, block=0, blocks_per_cu=0, steps_per_round=0):
-    _check(ctx, load().mc_set_launch(ctx, block, blocks_per_cu, steps_per_round))
+def mc_set_layout(ctx, layout):
+    _check(ctx, load().mc_set_layout(ctx, layout))
+
+
+def mc_get_layout(ctx):
+    lay, npal = C.c_int(), C.c_int()
+    _check(ctx, load().mc_get_layout(ctx, C.byref(lay), C.byref(npal)))
+    return lay.value, npal.value
+
+
+def mc_set_launch(ctx, block=0, blocks_per_cu=0, event_batch=0):
+    _check(ctx, load().mc_set_launch(ctx, block, blocks_per_cu, event_batch))
 
 
 def mc_tally_scale():
@@ -285,8 +329,14 @@ class Projector:
     def tables(self, n_mat):
         return mc_get_tables(self.ctx, n_mat)
 
-    def set_launch(self, block=0, blocks_per_cu=0, steps_per_round=0):
-        mc_set_launch(self.ctx, block, blocks_per_cu, steps_per_round)
+    def set_layout(self, layout):
+        mc_set_layout(self.ctx, layout)
+
+    def layout(self):
+        return mc_get_layout(self.ctx)
+
+    def set_launch(self, block=0, blocks_per_cu=0, event_batch=0):
+        mc_set_launch(self.ctx, block, blocks_per_cu, event_batch)
 
     def stats(self, enable=None):
         if enable is not None:

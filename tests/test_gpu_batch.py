@@ -1,0 +1,138 @@
+"""Batched projections: one persistent launch over a job table (many angles,
+phantoms of different sizes and layouts, uneven photon counts), direct or
+replayed from a captured hipGraph.  Each job's images must be bitwise those
+of a single projection with the same inputs, and a sample of jobs must match
+the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13191_amd import inputs, mcx
+from test_gpu_parity import check_images, say
+
+pytestmark = pytest.mark.gpu
+
+GEO = dict(sod_mm=400.0, sdd_mm=800.0, nu=48, nv=40, pu_mm=2.0, pv_mm=2.0, snu=12, snv=10,
+           step_mm=0.8, flags=0)
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on the MI355X box")
+    return torch
+
+
+def phantoms():
+    rng = np.random.default_rng(4)
+    keys = rng.integers(0, 200, size=(9, 14, 17))
+    many = rng.integers(0, 5, size=(10, 12, 13)).astype(np.uint8)
+    return [
+        (*inputs.cylinder_phantom(32, 2.0, radius_mm=20.0), 2.0),          # 2-entry palette
+        (*inputs.ellipsoid_phantom(40, 1.5, seed=5), 1.5),                  # ellipsoid palette
+        ((keys % 5).astype(np.uint8), (0.1 + 0.013 * keys).astype(np.float32), 3.0),   # 200
+        (many, rng.uniform(0, 2, size=many.shape).astype(np.float32), 2.5),  # generic
+    ]
+
+
+def jobs_for(handles):
+    counts = [0, 1, 777, 50_000, 120_003, 65, 33_000, 2_000, 90_001, 10, 64, 150_000]
+    jobs, off = [], 0
+    np_, ns_ = GEO["nu"] * GEO["nv"], GEO["snu"] * GEO["snv"]
+    for i, n in enumerate(counts):
+        jobs.append(dict(phantom=handles[i % len(handles)], angle_rad=0.37 * i, n_photons=n,
+                         seed=1000 + 7 * i, primary_offset=off, scatter_offset=off + np_))
+        off += np_ + ns_ + 3
+    return jobs, off
+
+
+def test_batch_equals_single_projections(torch_gpu):
+    torch = torch_gpu
+    ph = phantoms()
+    spec = inputs.kramers_spectrum(110, 1.5)
+    g = mcx.Projector(0)
+    g.set_spectrum(*spec)
+    g.set_geometry(**GEO)
+    g.load_phantom(ph[0][0], ph[0][1], ph[0][2])
+    handles = [0] + [mcx.mc_phantom_add(g.ctx, a, b, h) for a, b, h in ph[1:]]
+    assert handles == [0, 1, 2, 3]
+    jobs, total = jobs_for(handles)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # references: each job alone, through the single-projection entry point
+    refs = []
+    singles = []
+    for k, (a, b, h) in enumerate(ph):
+        s = mcx.Projector(0)
+        s.set_spectrum(*spec)
+        s.set_geometry(**GEO)
+        s.load_phantom(a, b, h)
+        singles.append(s)
+    for j in jobs:
+        say("single", j["phantom"], j["n_photons"])
+        refs.append(singles[j["phantom"]].project(j["angle_rad"], j["n_photons"], j["seed"]))
+
+    np_, ns_ = GEO["nu"] * GEO["nv"], GEO["snu"] * GEO["snv"]
+    out = torch.full((total,), 123, dtype=torch.int64, device=dev)
+
+    def check(tag):
+        host = out.cpu().numpy()
+        for j, (rp, rs) in zip(jobs, refs):
+            p = host[j["primary_offset"]:j["primary_offset"] + np_].reshape(GEO["nv"], GEO["nu"])
+            s = host[j["scatter_offset"]:j["scatter_offset"] + ns_].reshape(GEO["snv"], GEO["snu"])
+            assert np.array_equal(p, rp) and np.array_equal(s, rs), (tag, j)
+        # the gaps between images were cleared too
+        for j in jobs:
+            gap = host[j["scatter_offset"] + ns_:j["scatter_offset"] + ns_ + 3]
+            assert np.all(gap == 0)
+
+    say("batch direct")
+    mcx.mc_project_batch(g.ctx, jobs, out, total, flags=0, stream=stream)
+    torch.cuda.synchronize()
+    check("direct")
+    for rep in range(3):
+        say("batch graph replay", rep)
+        out.fill_(-5)
+        mcx.mc_project_batch(g.ctx, jobs, out, total, flags=mcx.MC_BATCH_GRAPH, stream=stream)
+        torch.cuda.synchronize()
+        check(f"graph {rep}")
+        # eager work between replays
+        singles[1].project(0.1, 10_000, 3)
+    # a changed job table replays the same graph with new contents
+    jobs2 = [dict(j, seed=j["seed"] + 1) for j in jobs]
+    mcx.mc_project_batch(g.ctx, jobs2, out, total, flags=mcx.MC_BATCH_GRAPH, stream=stream)
+    torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    j = jobs2[4]
+    rp, rs = singles[j["phantom"]].project(j["angle_rad"], j["n_photons"], j["seed"])
+    assert np.array_equal(host[j["primary_offset"]:j["primary_offset"] + np_].reshape(rp.shape), rp)
+
+    # two jobs against the oracle
+    for j in (jobs[4], jobs[7]):
+        a, b, h = ph[j["phantom"]]
+        o = oracle.Oracle()
+        o.load_phantom(a, b, h)
+        o.set_geometry(**GEO)
+        o.set_spectrum(*spec)
+        po, so = o.project(j["angle_rad"], j["n_photons"], j["seed"], threads=8)
+        rp, rs = refs[jobs.index(j)]
+        check_images(f"batch job {jobs.index(j)}", rp, rs, po, so)
+
+
+def test_batch_errors(torch_gpu):
+    torch = torch_gpu
+    g = mcx.Projector(0)
+    g.set_spectrum(*inputs.mono_spectrum(60.0))
+    g.set_geometry(**GEO)
+    a, b = inputs.cylinder_phantom(16, 2.0)
+    g.load_phantom(a, b, 2.0)
+    out = torch.zeros(10, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(mcx.MCXError):     # images do not fit
+        mcx.mc_project_batch(g.ctx, [dict(phantom=0, angle_rad=0.0, n_photons=10, seed=0,
+                                          primary_offset=0, scatter_offset=0)], out, 10)
+    big = torch.zeros(5000, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(mcx.MCXError):     # unknown phantom
+        mcx.mc_project_batch(g.ctx, [dict(phantom=3, angle_rad=0.0, n_photons=10, seed=0,
+                                          primary_offset=0, scatter_offset=2000)], big, 5000)

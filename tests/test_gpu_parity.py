@@ -185,7 +185,7 @@ def test_launch_shape_invariance(gpu):
     g.set_geometry(**w["geometry"])
     g.set_spectrum(*inputs.kramers_spectrum(100, 1.0))
     ref = g.project(0.7, 300_000, 11)
-    for block, bpc, spr in [(64, 1, 1), (128, 2, 7), (256, 0, 1024), (192, 3, 33), (64, 8, 64)]:
+    for block, bpc, spr in [(64, 1, 1), (128, 2, 7), (256, 0, 64), (192, 3, 33), (64, 8, 48)]:
         say("launch", block, bpc, spr)
         g.set_launch(block, bpc, spr)
         p, s = g.project(0.7, 300_000, 11)
@@ -250,3 +250,45 @@ def test_errors(gpu):
     with pytest.raises(mcx.MCXError) as e:
         g.project(0.0, 10, 0)
     assert e.value.code == mcx.MC_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("shape,n_distinct", [((13, 9, 7), 12), ((21, 18, 11), 200),
+                                              ((33, 5, 17), 3000)])
+def test_layouts_bitwise(gpu, shape, n_distinct):
+    """Every device layout (per-lane palette table, shared palette, id + density)
+    gives the oracle's images, on shapes that are not multiples of the brick."""
+    rng = np.random.default_rng(n_distinct)
+    keys = rng.integers(0, n_distinct, size=shape)
+    ids = (keys % 5).astype(np.uint8)
+    rho = (0.2 + 0.01 * keys).astype(np.float32)
+    geo = dict(sod_mm=400.0, sdd_mm=800.0, nu=36, nv=28, pu_mm=3.0, pv_mm=3.0, snu=12, snv=7,
+               step_mm=0.9, flags=0)
+    say("layouts", shape, n_distinct)
+    o = oracle.Oracle()
+    o.load_phantom(ids, rho, 2.5)
+    o.set_geometry(**geo)
+    o.set_spectrum(*inputs.kramers_spectrum(120, 1.0))
+    po, so = o.project(2.0, 150_000, 31, threads=8)
+    seen = set()
+    for lay in [mcx.MC_LAYOUT_AUTO, mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED,
+                mcx.MC_LAYOUT_GENERIC]:
+        g = mcx.Projector(0)
+        g.set_layout(lay)
+        try:
+            g.load_phantom(ids, rho, 2.5)
+        except mcx.MCXError as e:
+            assert n_distinct > 256 and lay in (mcx.MC_LAYOUT_PALETTE_LANE,
+                                                mcx.MC_LAYOUT_PALETTE_SHARED)
+            assert e.code == mcx.MC_E_INVALID_ARG
+            continue
+        used, npal = g.layout()
+        seen.add(used)
+        g.set_geometry(**geo)
+        g.set_spectrum(*inputs.kramers_spectrum(120, 1.0))
+        say("layout requested", lay, "used", used, "palette", npal)
+        pg, sg = g.project(2.0, 150_000, 31)
+        assert np.array_equal(pg, po) and np.array_equal(sg, so), (lay, used)
+        g.close()
+    if n_distinct <= 32:
+        assert seen == {mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED,
+                        mcx.MC_LAYOUT_GENERIC}
