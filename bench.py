@@ -24,8 +24,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
-GATHER_BYTES_PER_STEP = 5        # uint8 material id + fp32 density per voxel lookup
+# 32-bit VALU issue peak (non-packed): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# arithmetic of one fixed-step march step as the transport specifies it:
+# step start and clipped end (4), step length and midpoint (3), voxel
+# coordinates (6), clamped indices (6), voxel address (4), optical depth and
+# the two tests (4), step advance (1)
+ALU_OPS_PER_STEP = 28
 TALLY_BYTES = 8                  # one int64 atomic add per detected photon
+COUNTERS = os.path.join(ROOT, "profiles", "transport_ellipsoids256_poly_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2201_13191_amd", "csrc", f)
+                  for f in ("transport.hip", "kernel_params.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, layout_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter record, if it
+    was taken on this exact kernel source and workload; else None."""
+    try:
+        rec = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def log(*a):
@@ -109,8 +138,11 @@ def main():
     torch.cuda.synchronize()
     st = g.stats()
     g.stats(False)
-    alg_bytes = st["steps"] * GATHER_BYTES_PER_STEP + \
+    layout, n_pal = g.layout()
+    gather_bytes = 1 if layout != mcx.MC_LAYOUT_GENERIC else 5   # bytes per voxel lookup
+    alg_bytes = st["steps"] * gather_bytes + \
         (st["primary_hits"] + st["scatter_hits"]) * TALLY_BYTES
+    alg_ops = st["steps"] * ALU_OPS_PER_STEP
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):
@@ -130,7 +162,8 @@ def main():
     wall = t1 - t0
     step_ms = [a.elapsed_time(b) for a, b in ev]
     launch_s = float(np.mean(step_ms)) * 1e-3
-    achieved = alg_bytes / launch_s / 1e9
+    achieved = alg_ops / launch_s / 1e12
+    gather_gbs = alg_bytes / launch_s / 1e9
     log(f"{n * args.steps / wall:.4g} histories/s, {launch_s * 1e3:.2f} ms per step (events), "
         f"steps/history {st['steps'] / max(st['histories'], 1):.1f}")
 
@@ -165,16 +198,21 @@ def main():
             "tallies": "int64 fixed point",
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "T op/s",
+            "frac": achieved / (VALU_PEAK_OPS / 1e12),
+            "traffic": measured_traffic(args.workload, gather_bytes),
             "kernel": "transport_kernel",
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_ops_per_launch": alg_ops,
+            "ops_per_step": ALU_OPS_PER_STEP,
             "launch_ms": launch_s * 1e3,
             "steps_per_history": st["steps"] / max(st["histories"], 1),
+            "layout": {0: "auto", 1: "palette-lane", 2: "palette-shared", 3: "generic"}[layout],
+            "gather": {"algorithmic_bytes_per_launch": alg_bytes,
+                       "bytes_per_step": gather_bytes, "achieved_GBs": gather_gbs,
+                       "hbm_peak_GBs": HBM_PEAK_GBS, "frac": gather_gbs / HBM_PEAK_GBS},
         },
         "cpu_baseline": cpu,
     }

@@ -233,6 +233,52 @@ mc_status mc_get_layout(mc_ctx *ctx, int *layout, int *palette_size);
  * Results never depend on these. */
 mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int event_batch);
 
+/* Dimensions of the loaded object (handle 0) and of the panel and scatter grid. */
+mc_status mc_get_shape(mc_ctx *ctx, int *nx, int *ny, int *nz, int *nu, int *nv, int *snu,
+                       int *snv);
+
+/* Result of mc_autotune. */
+typedef struct mc_tuning {
+    int32_t block, blocks_per_cu, event_batch;
+    int32_t from_cache;      /* 1: taken from the cache, nothing was timed          */
+    int32_t candidates;      /* launch shapes timed                                 */
+    int32_t rejected;        /* shapes whose images differed bitwise (must be 0)    */
+    double ms;               /* best time of one projection of n_photons            */
+    double histories_per_s;
+} mc_tuning;
+
+/* Launch-shape autotuner: times block size x blocks per CU x event batch on
+ * the context's current object, panel and spectrum (n_photons of projection
+ * angle_rad with `seed`), checks that every shape reproduces the first
+ * shape's images bitwise (rejecting any that does not), applies the fastest
+ * with mc_set_launch and appends it to the JSON-lines file cache_path (may be
+ * NULL).  If cache_path already holds an entry for this device and workload
+ * class, that entry is applied and nothing is timed.  Uses the GPU. */
+mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t seed,
+                      const char *cache_path, mc_tuning *out);
+
+/* ---- post-processing of scatter images (section II-C-3 and II-C-4) ----
+ * Stream-ordered kernels on device float images [ny][nx]. */
+
+/* d_out[i] = (float)(d_in[i] * scale): Q43.20 tallies to float (scale =
+ * 2^-20 gives keV; divide further by the photon count to normalise). */
+mc_status mc_tally_to_float_async(mc_ctx *ctx, const int64_t *d_in, float *d_out, uint64_t n,
+                                  double scale, void *stream);
+/* Savitzky-Golay smoothing (the paper uses cubic order): least-squares
+ * polynomial of degree `order` over `window` (odd, <= 31) samples, applied
+ * along rows then columns, samples beyond an edge mirrored about the edge
+ * sample.  d_tmp: caller scratch of nx*ny floats.  fp32. */
+mc_status mc_savgol_async(mc_ctx *ctx, const float *d_in, float *d_out, float *d_tmp, int nx,
+                          int ny, int window, int order, void *stream);
+/* Cubic up-sampling by an integer factor (the paper's (576,800) -> (2304,3200)
+ * cubic interpolation): Keys' kernel with a = -0.5, output pixel i at input
+ * coordinate (i + 0.5)/factor - 0.5, edges clamped; d_out is
+ * [ny*factor][nx*factor].  fp32. */
+mc_status mc_upsample_cubic_async(mc_ctx *ctx, const float *d_in, float *d_out, int nx, int ny,
+                                  int factor, void *stream);
+/* The fp32 Savitzky-Golay weights mc_savgol_async uses (host only). */
+mc_status mc_savgol_weights(int window, int order, float *weights);
+
 /* keV per least significant bit of a tally: 2^-20. */
 double mc_tally_scale(void);
 

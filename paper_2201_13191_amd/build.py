@@ -21,7 +21,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contr
              "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
-SOURCES = [("transport.hip", "hip"), ("runtime.hip", "hip"), ("tables.cpp", "cxx")]
+SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("runtime.hip", "hip"),
+           ("tables.cpp", "cxx"), ("autotune.cpp", "hiphost")]
 
 
 def _compile(src, kind):
@@ -29,6 +30,8 @@ def _compile(src, kind):
     path = os.path.join(CSRC, src)
     if kind == "hip":
         cmd = ["hipcc", "-x", "hip", *HIP_FLAGS, "-c", path, "-o", out]
+    elif kind == "hiphost":   # host-only C++ against the HIP runtime API
+        cmd = ["hipcc", *CXX_FLAGS, "-c", path, "-o", out]
     else:
         cmd = ["g++", *CXX_FLAGS, "-c", path, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)

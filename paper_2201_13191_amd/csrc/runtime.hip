@@ -30,6 +30,11 @@ hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int bl
 int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats);
 hipError_t launch_clear(unsigned long long *a, size_t na, unsigned long long *b, size_t nb,
                         hipStream_t stream);
+hipError_t launch_savgol(const float *in, float *out, float *tmp, int nx, int ny, int window,
+                         const float *coeffs, hipStream_t s);
+hipError_t launch_upsample(const float *in, float *out, int nx, int ny, int f, hipStream_t s);
+hipError_t launch_tally_to_float(const int64_t *in, float *out, uint64_t n, double scale,
+                                 hipStream_t s);
 }  // namespace mcx
 
 using namespace mcx;
@@ -38,7 +43,7 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 32;
+constexpr int kDefaultEventBatch = 40;
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or
@@ -964,6 +969,61 @@ mc_status mc_set_launch(mc_ctx *c, int block, int blocks_per_cu, int event_batch
     c->block = block;
     c->blocks_per_cu = blocks_per_cu;
     c->event_batch = event_batch;
+    return MC_OK;
+}
+
+mc_status mc_get_shape(mc_ctx *c, int *nx, int *ny, int *nz, int *nu, int *nv, int *snu,
+                       int *snv) {
+    if (!c || !nx || !ny || !nz || !nu || !nv || !snu || !snv) return MC_E_INVALID_ARG;
+    if (!c->have_phantom || !c->have_geom) return fail(c, MC_E_STATE, "phantom and geometry must be set");
+    const Phantom &ph = c->phantoms[0];
+    *nx = ph.nx; *ny = ph.ny; *nz = ph.nz;
+    *nu = c->g.nu; *nv = c->g.nv; *snu = c->g.snu; *snv = c->g.snv;
+    return MC_OK;
+}
+
+mc_status mc_tally_to_float_async(mc_ctx *c, const int64_t *d_in, float *d_out, uint64_t n,
+                                  double scale, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if ((!d_in || !d_out) && n) return fail(c, MC_E_INVALID_ARG, "null buffer");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    if (n == 0) return MC_OK;
+    const hipError_t e = launch_tally_to_float(d_in, d_out, n, scale, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(c, e, "tally to float");
+}
+
+mc_status mc_savgol_async(mc_ctx *c, const float *d_in, float *d_out, float *d_tmp, int nx, int ny,
+                          int window, int order, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_in || !d_out || !d_tmp || nx < 1 || ny < 1 || nx > 65536 || ny > 65535)
+        return fail(c, MC_E_INVALID_ARG, "bad image");
+    if (window < 1 || window > 31 || window % 2 == 0 || order < 0 || order >= window)
+        return fail(c, MC_E_INVALID_ARG, "window must be odd, 1..31, and > order");
+    float co[31];
+    savgol_weights(window, order, co);
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    const hipError_t e = launch_savgol(d_in, d_out, d_tmp, nx, ny, window, co, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(c, e, "savgol");
+}
+
+mc_status mc_upsample_cubic_async(mc_ctx *c, const float *d_in, float *d_out, int nx, int ny,
+                                  int factor, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_in || !d_out || nx < 1 || ny < 1 || factor < 1 || factor > 16 ||
+        (int64_t)nx * factor > 65536 || (int64_t)ny * factor > 65535)
+        return fail(c, MC_E_INVALID_ARG, "bad image or factor");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    const hipError_t e = launch_upsample(d_in, d_out, nx, ny, factor, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(c, e, "cubic upsample");
+}
+
+mc_status mc_savgol_weights(int window, int order, float *weights) {
+    if (!weights || window < 1 || window > 31 || window % 2 == 0 || order < 0 || order >= window)
+        return MC_E_INVALID_ARG;
+    savgol_weights(window, order, weights);
     return MC_OK;
 }
 

@@ -13,6 +13,7 @@
 #include "tables.hpp"
 
 #include <cmath>
+#include <utility>
 
 namespace mcx {
 namespace {
@@ -110,6 +111,48 @@ double rayleigh_b(float z_eff) {
     const double r = 0.885 * 0.529177210903 / std::cbrt((double)z_eff);
     const double t = 6.283185307179586 * r;
     return t * t;
+}
+
+void savgol_weights(int window, int order, float *w) {
+    // least-squares polynomial of degree `order` on offsets -h..h, value at 0:
+    // row 0 of (A^T A)^-1 A^T with A[j][k] = j^k, solved by Gauss-Jordan in
+    // long double on the (order+1)^2 normal matrix
+    const int h = window / 2, m = order + 1;
+    long double N[16][16] = {}, inv[16][16] = {};
+    for (int r = 0; r < m; ++r)
+        for (int cc = 0; cc < m; ++cc) {
+            long double s = 0.0L;
+            for (int j = -h; j <= h; ++j) s += std::pow((long double)j, r + cc);
+            N[r][cc] = s;
+        }
+    for (int r = 0; r < m; ++r) inv[r][r] = 1.0L;
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (std::fabs(N[r][col]) > std::fabs(N[piv][col])) piv = r;
+        for (int cc = 0; cc < m; ++cc) {
+            std::swap(N[col][cc], N[piv][cc]);
+            std::swap(inv[col][cc], inv[piv][cc]);
+        }
+        const long double d = N[col][col];
+        for (int cc = 0; cc < m; ++cc) {
+            N[col][cc] /= d;
+            inv[col][cc] /= d;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == col) continue;
+            const long double f = N[r][col];
+            for (int cc = 0; cc < m; ++cc) {
+                N[r][cc] -= f * N[col][cc];
+                inv[r][cc] -= f * inv[col][cc];
+            }
+        }
+    }
+    for (int j = -h; j <= h; ++j) {
+        long double s = 0.0L;
+        for (int k = 0; k < m; ++k) s += inv[0][k] * std::pow((long double)j, k);
+        w[j + h] = (float)s;
+    }
 }
 
 void spectrum_thresholds(const float *w, int n, std::vector<uint64_t> &thr) {

@@ -31,4 +31,8 @@ double rayleigh_b(float z_eff);
 // cumulative weight, thr[n-1] = 2^32; the bin of draw x is the first k with x < thr[k].
 void spectrum_thresholds(const float *w, int n, std::vector<uint64_t> &thr);
 
+// Savitzky-Golay weights (window odd <= 31, order < window): value at the
+// window centre of the least-squares polynomial, as fp32.
+void savgol_weights(int window, int order, float *w);
+
 }  // namespace mcx

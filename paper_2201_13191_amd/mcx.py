@@ -26,7 +26,9 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_set_geometry", "mc_set_spectrum", "mc_set_detector_response", "mc_project",
            "mc_project_async", "mc_project_range_async", "mc_debug_histories", "mc_test_sample",
            "mc_set_stats", "mc_get_stats", "mc_get_tables", "mc_set_layout", "mc_get_layout",
-           "mc_set_launch", "mc_tally_scale", "mc_phantom_add", "mc_project_batch"]
+           "mc_set_launch", "mc_tally_scale", "mc_phantom_add", "mc_project_batch",
+           "mc_get_shape", "mc_autotune", "mc_tally_to_float_async", "mc_savgol_async",
+           "mc_upsample_cubic_async", "mc_savgol_weights"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -48,6 +50,12 @@ class mc_job(C.Structure):
     _fields_ = [("phantom", C.c_int32), ("angle_rad", C.c_float), ("n_photons", C.c_uint64),
                 ("seed", C.c_uint64), ("primary_offset", C.c_uint64),
                 ("scatter_offset", C.c_uint64)]
+
+
+class mc_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("event_batch", C.c_int32),
+                ("from_cache", C.c_int32), ("candidates", C.c_int32), ("rejected", C.c_int32),
+                ("ms", C.c_double), ("histories_per_s", C.c_double)]
 
 
 class mc_stats(C.Structure):
@@ -97,6 +105,12 @@ def load():
         "mc_tally_scale": ([], C.c_double),
         "mc_phantom_add": ([P, P, P, I, I, I, F, C.POINTER(I)], I),
         "mc_project_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_uint32, P], I),
+        "mc_get_shape": ([P] + [C.POINTER(I)] * 7, I),
+        "mc_tally_to_float_async": ([P, P, P, U64, C.c_double, P], I),
+        "mc_savgol_async": ([P, P, P, P, I, I, I, I, P], I),
+        "mc_upsample_cubic_async": ([P, P, P, I, I, I, P], I),
+        "mc_savgol_weights": ([I, I, P], I),
+        "mc_autotune": ([P, F, U64, U64, C.c_char_p, C.POINTER(mc_tuning)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -268,6 +282,42 @@ def mc_get_layout(ctx):
 
 def mc_set_launch(ctx, block=0, blocks_per_cu=0, event_batch=0):
     _check(ctx, load().mc_set_launch(ctx, block, blocks_per_cu, event_batch))
+
+
+def mc_get_shape(ctx):
+    v = [C.c_int() for _ in range(7)]
+    _check(ctx, load().mc_get_shape(ctx, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def mc_autotune(ctx, angle, n_photons, seed, cache_path=None):
+    t = mc_tuning()
+    path = cache_path.encode() if cache_path else None
+    _check(ctx, load().mc_autotune(ctx, angle, n_photons, seed, path, C.byref(t)))
+    return {n: getattr(t, n) for n, _ in mc_tuning._fields_}
+
+
+def mc_tally_to_float_async(ctx, d_in, d_out, n, scale, stream=None):
+    _check(ctx, load().mc_tally_to_float_async(ctx, _dev(d_in), _dev(d_out), n, scale,
+                                               _stream(stream)))
+
+
+def mc_savgol_async(ctx, d_in, d_out, d_tmp, nx, ny, window, order, stream=None):
+    _check(ctx, load().mc_savgol_async(ctx, _dev(d_in), _dev(d_out), _dev(d_tmp), nx, ny, window,
+                                       order, _stream(stream)))
+
+
+def mc_upsample_cubic_async(ctx, d_in, d_out, nx, ny, factor, stream=None):
+    _check(ctx, load().mc_upsample_cubic_async(ctx, _dev(d_in), _dev(d_out), nx, ny, factor,
+                                               _stream(stream)))
+
+
+def mc_savgol_weights(window, order):
+    w = np.zeros(window, np.float32)
+    rc = load().mc_savgol_weights(window, order, _np(w))
+    if rc:
+        raise MCXError(rc, "bad window/order")
+    return w
 
 
 def mc_tally_scale():

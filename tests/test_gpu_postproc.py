@@ -1,0 +1,60 @@
+"""GPU Savitzky-Golay smoothing and cubic up-sampling against the fp64 oracle.
+
+Tolerance: fp32 kernels accumulate at most 31 (smoothing) or 16 (up-sampling)
+products of O(1) weights; each rounding is <= 2^-24 relative, so the error is
+below 1e-5 of the image's largest magnitude (written as |gpu - oracle| <=
+1e-5 * max|oracle|)."""
+import numpy as np
+import pytest
+
+from oracle import postproc as pp
+from paper_2201_13191_amd import mcx
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on the MI355X box")
+    return torch, mcx.mc_create(0)
+
+
+@pytest.mark.parametrize("shape,window", [((128, 128), 7), ((37, 53), 11), ((1, 9), 5),
+                                          ((64, 3), 31)])
+def test_savgol_gpu(env, shape, window):
+    torch, ctx = env
+    say("savgol", shape, window)
+    img = np.random.default_rng(1).gamma(2.0, 3.0, size=shape).astype(np.float32)
+    d_in = torch.from_numpy(img).cuda()
+    d_out = torch.empty_like(d_in)
+    d_tmp = torch.empty_like(d_in)
+    mcx.mc_savgol_async(ctx, d_in, d_out, d_tmp, shape[1], shape[0], window, 3)
+    torch.cuda.synchronize()
+    ref = pp.savgol_2d(img.astype(np.float64), window, 3)
+    assert np.abs(d_out.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape,f", [((128, 128), 2), ((13, 29), 3), ((1, 1), 4)])
+def test_upsample_gpu(env, shape, f):
+    torch, ctx = env
+    say("upsample", shape, f)
+    img = np.random.default_rng(2).normal(size=shape).astype(np.float32)
+    d_in = torch.from_numpy(img).cuda()
+    d_out = torch.empty((shape[0] * f, shape[1] * f), dtype=torch.float32, device="cuda")
+    mcx.mc_upsample_cubic_async(ctx, d_in, d_out, shape[1], shape[0], f)
+    torch.cuda.synchronize()
+    ref = pp.upsample_2d(img.astype(np.float64), f)
+    assert np.abs(d_out.cpu().numpy() - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1.0)
+
+
+def test_tally_to_float(env):
+    torch, ctx = env
+    v = np.array([0, 1, -3, 2 ** 40 + 12345, 60 * 2 ** 20], np.int64)
+    d_in = torch.from_numpy(v).cuda()
+    d_out = torch.empty(5, dtype=torch.float32, device="cuda")
+    mcx.mc_tally_to_float_async(ctx, d_in, d_out, 5, 2.0 ** -20)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_out.cpu().numpy(), (v.astype(np.float64) * 2.0 ** -20).astype(np.float32))
