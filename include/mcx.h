@@ -279,6 +279,80 @@ mc_status mc_upsample_cubic_async(mc_ctx *ctx, const float *d_in, float *d_out, 
 /* The fp32 Savitzky-Golay weights mc_savgol_async uses (host only). */
 mc_status mc_savgol_weights(int window, int order, float *weights);
 
+/* ---- learned scatter denoiser / up-sampler: network kernels ----
+ * A 2-D U-Net (bf16 weights and activations, fp32 accumulation on the
+ * matrix cores) replaces the smoothing and interpolation of the paper's
+ * correction loop (section II-C-3/4) and is trained by these kernels.
+ * Activations are NHWC bf16 ([n][y][x][c], channels fastest) given as
+ * (pointer, channel stride ld, channel offset), so concatenated skip
+ * connections are channel slices of one buffer.  3x3 weights are bf16
+ * [cout_alloc][9][cin] with tap = 3*(dy+1) + (dx+1); cout_alloc = 32 when
+ * cout <= 32, else cout rounded up to 64; rows beyond cout are zero.
+ * Requirements (checked): cin, ldx, xoff multiples of 16, 16-byte aligned
+ * pointers, and the weight rows above.  All stream-ordered. */
+typedef struct mc_conv3x3 {
+    const uint16_t *x;      /* input activations                               */
+    int32_t ldx, xoff;
+    const uint16_t *w;      /* weights [cout_alloc][9][cin]                     */
+    const float *bias;      /* [cout] or NULL                                   */
+    uint16_t *y;            /* bf16 output (or NULL)                             */
+    int32_t ldy, yoff;
+    float *yf;              /* fp32 output [pixels][cout] (or NULL)              */
+    const uint16_t *mask;   /* output multiplied by (mask > 0) if not NULL       */
+    int32_t ldm, moff;
+    int32_t n, h, w_, cin, cout;
+    int32_t relu;           /* max(0, .) after the bias                          */
+    int32_t accumulate;     /* add to the existing bf16 output                   */
+} mc_conv3x3;
+
+/* y = act(conv3x3(x, w) + bias), zero padding, stride 1.  With the flipped,
+ * transposed weights of mc_nn_flip_weights_async and mask = the layer input,
+ * it computes a convolution's input gradient through the previous ReLU. */
+mc_status mc_nn_conv3x3_async(mc_ctx *ctx, const mc_conv3x3 *args, void *stream);
+/* dw[co][tap][ci] (fp32) = sum over pixels of dy[p][co] * x[p + tap][ci];
+ * deterministic (per-split partials summed in order).  workspace: at least
+ * (splits + 1) * 9 * cout * cin floats; cin, cout multiples of 16. */
+mc_status mc_nn_conv3x3_wgrad_async(mc_ctx *ctx, const uint16_t *x, int ldx, int xoff,
+                                    const uint16_t *dy, int ldy, int yoff, int n, int h, int w,
+                                    int cin, int cout, int splits, float *workspace, float *dw,
+                                    void *stream);
+/* db[c] = sum over npix pixels of dy[p][c] (fp32); workspace rows * c floats. */
+mc_status mc_nn_bias_grad_async(mc_ctx *ctx, const uint16_t *dy, int ldy, int yoff, int npix,
+                                int c, float *workspace, int rows, float *db, void *stream);
+/* wt[ci][tap][co] = w[co][8 - tap][ci], zero for co >= cout or ci >= cin;
+ * wt has cin_pad rows of 9 * cout_pad. */
+mc_status mc_nn_flip_weights_async(mc_ctx *ctx, const uint16_t *w, uint16_t *wt, int cout, int cin,
+                                   int cout_pad, int cin_pad, void *stream);
+/* 2x2 average pooling of x[n][h][w] into y[n][h/2][w/2]; backward: x is the
+ * pooled-size gradient, y the full-size one.  accumulate adds to y. */
+mc_status mc_nn_pool2_async(mc_ctx *ctx, const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
+                            int yoff, int n, int h, int w, int c, int backward, int accumulate,
+                            void *stream);
+/* nearest 2x up-sampling of x[n][h][w] into y[n][2h][2w]; backward: x is the
+ * [2h][2w] gradient, y[n][h][w] the sum of each 2x2 block. */
+mc_status mc_nn_upsample2_async(mc_ctx *ctx, const uint16_t *x, int ldx, int xoff, uint16_t *y,
+                                int ldy, int yoff, int n, int h, int w, int c, int backward,
+                                int accumulate, void *stream);
+/* partial[b] = sum over block b of (out[i*ldo] - target[i])^2 (blocks of 256);
+ * grad (if not NULL) channel goff of an NHWC buffer = bf16(2 (out - t) / n * gscale). */
+mc_status mc_nn_mse_async(mc_ctx *ctx, const float *out, int ldo, const float *target, uint64_t n,
+                          uint16_t *grad, int ldg, int goff, float gscale, float *partial,
+                          void *stream);
+/* Adam step t >= 1 on fp32 master weights p with gradient g * gscale; moments
+ * m, v; writes the bf16 copy p_bf16 (may be NULL). */
+mc_status mc_nn_adam_async(mc_ctx *ctx, float *p, const float *g, float *m, float *v,
+                           uint16_t *p_bf16, uint64_t n, float lr, float beta1, float beta2,
+                           float eps, int step, float gscale, void *stream);
+/* g[p][goff + c] = 0 where y[p][yoff + c] <= 0 (gradient through a ReLU with
+ * output y), for p < npix, c < ch. */
+mc_status mc_nn_relu_mask_async(mc_ctx *ctx, uint16_t *g, int ldg, int goff, const uint16_t *y,
+                                int ldy, int yoff, uint64_t npix, int ch, void *stream);
+mc_status mc_nn_cast_bf16_async(mc_ctx *ctx, const float *in, uint16_t *out, uint64_t n,
+                                void *stream);
+/* out[p*ld + coff] = bf16(in[p] * scale) for p < npix. */
+mc_status mc_nn_pack_channel_async(mc_ctx *ctx, const float *in, uint64_t npix, float scale,
+                                   uint16_t *out, int ld, int coff, void *stream);
+
 /* keV per least significant bit of a tally: 2^-20. */
 double mc_tally_scale(void);
 

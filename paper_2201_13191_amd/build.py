@@ -21,7 +21,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contr
              "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
-SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("runtime.hip", "hip"),
+SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
+           ("runtime.hip", "hip"),
            ("tables.cpp", "cxx"), ("autotune.cpp", "hiphost")]
 
 

@@ -17,6 +17,7 @@
 
 #include "../../include/mcx.h"
 #include "kernel_params.hpp"
+#include "nn_params.hpp"
 #include "tables.hpp"
 
 namespace mcx {
@@ -35,6 +36,24 @@ hipError_t launch_savgol(const float *in, float *out, float *tmp, int nx, int ny
 hipError_t launch_upsample(const float *in, float *out, int nx, int ny, int f, hipStream_t s);
 hipError_t launch_tally_to_float(const int64_t *in, float *out, uint64_t n, double scale,
                                  hipStream_t s);
+hipError_t nn_conv3x3(const ConvArgs &a, hipStream_t s);
+hipError_t nn_wgrad(const WgradArgs &a, float *tmp, float *dw, hipStream_t s);
+hipError_t nn_colsum(const uint16_t *dy, int ldy, int yoff, int npix, int c, float *partial,
+                     int rows, float *out, hipStream_t s);
+hipError_t nn_flip(const uint16_t *w, uint16_t *wt, int cout, int cin, int cout_pad, int cin_pad,
+                   hipStream_t s);
+hipError_t nn_resample(int op, const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
+                       int yoff, int n, int h, int w, int c, int backward, int accumulate,
+                       hipStream_t s);
+hipError_t nn_mse(const float *out, int ldo, const float *t, int64_t n, uint16_t *g, int ldg,
+                  int goff, float gscale, float *partial, hipStream_t s);
+hipError_t nn_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr,
+                   float b1, float b2, float eps, float c1, float c2, float gscale, hipStream_t s);
+hipError_t nn_cast_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
+hipError_t nn_relu_mask(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy, int yoff,
+                        int64_t npix, int c, hipStream_t s);
+hipError_t nn_pack_channel(const float *in, int64_t npix, float scale, uint16_t *out, int ld,
+                           int coff, hipStream_t s);
 }  // namespace mcx
 
 using namespace mcx;
@@ -1025,6 +1044,144 @@ mc_status mc_savgol_weights(int window, int order, float *weights) {
         return MC_E_INVALID_ARG;
     savgol_weights(window, order, weights);
     return MC_OK;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+#define NN_RUN(c, expr, what)                                                 \
+    do {                                                                      \
+        mc_status rc_ = use_device(c);                                        \
+        if (rc_) return rc_;                                                  \
+        const hipError_t e_ = (expr);                                         \
+        return e_ == hipSuccess ? MC_OK : hip_fail(c, e_, what);              \
+    } while (0)
+
+mc_status mc_nn_conv3x3_async(mc_ctx *c, const mc_conv3x3 *a, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!a || !a->x || !a->w || (!a->y && !a->yf)) return fail(c, MC_E_INVALID_ARG, "null buffer");
+    if (a->n < 1 || a->h < 1 || a->w_ < 1 || a->cin < 16 || a->cin % 16 || a->cout < 1 ||
+        (int64_t)a->n * a->h * a->w_ >= ((int64_t)1 << 31))
+        return fail(c, MC_E_INVALID_ARG, "conv: bad shape (cin must be a multiple of 16)");
+    if (a->ldx % 16 || a->xoff % 16 || a->xoff + a->cin > a->ldx || !aligned16(a->x) ||
+        !aligned16(a->w))
+        return fail(c, MC_E_INVALID_ARG, "conv: input slice must be 16-channel aligned");
+    if (a->y && (a->yoff < 0 || a->yoff + a->cout > a->ldy))
+        return fail(c, MC_E_INVALID_ARG, "conv: output slice outside its buffer");
+    if (a->mask && (a->moff < 0 || a->moff + a->cout > a->ldm))
+        return fail(c, MC_E_INVALID_ARG, "conv: mask slice outside its buffer");
+    ConvArgs k;
+    k.x = a->x; k.ldx = a->ldx; k.xoff = a->xoff; k.w = a->w; k.bias = a->bias;
+    k.y = a->y; k.ldy = a->ldy; k.yoff = a->yoff; k.yf = a->yf;
+    k.mask = a->mask; k.ldm = a->ldm; k.moff = a->moff;
+    k.n = a->n; k.h = a->h; k.w_ = a->w_; k.cin = a->cin; k.cout = a->cout;
+    k.relu = a->relu; k.accumulate = a->accumulate;
+    NN_RUN(c, nn_conv3x3(k, (hipStream_t)stream), "conv3x3");
+}
+
+mc_status mc_nn_conv3x3_wgrad_async(mc_ctx *c, const uint16_t *x, int ldx, int xoff,
+                                    const uint16_t *dy, int ldy, int yoff, int n, int h, int w,
+                                    int cin, int cout, int splits, float *ws, float *dw,
+                                    void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!x || !dy || !ws || !dw || n < 1 || h < 1 || w < 1 || cin < 16 || cin % 16 ||
+        cout < 16 || cout % 16 || splits < 1 || splits > 4096)
+        return fail(c, MC_E_INVALID_ARG, "wgrad: bad arguments (cin, cout multiples of 16)");
+    if (ldx % 16 || xoff % 16 || xoff + cin > ldx || yoff + cout > ldy || !aligned16(x))
+        return fail(c, MC_E_INVALID_ARG, "wgrad: bad slices");
+    WgradArgs k;
+    k.x = x; k.ldx = ldx; k.xoff = xoff; k.dy = dy; k.ldy = ldy; k.yoff = yoff;
+    k.n = n; k.h = h; k.w_ = w; k.cin = cin; k.cout = cout; k.splits = splits;
+    k.partial = ws;
+    float *tmp = ws + (size_t)splits * 9 * cout * cin;
+    NN_RUN(c, nn_wgrad(k, tmp, dw, (hipStream_t)stream), "wgrad");
+}
+
+mc_status mc_nn_bias_grad_async(mc_ctx *c, const uint16_t *dy, int ldy, int yoff, int npix, int ch,
+                                float *ws, int rows, float *db, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!dy || !ws || !db || npix < 1 || ch < 1 || rows < 1 || rows > 65535 || yoff + ch > ldy)
+        return fail(c, MC_E_INVALID_ARG, "bias grad: bad arguments");
+    NN_RUN(c, nn_colsum(dy, ldy, yoff, npix, ch, ws, rows, db, (hipStream_t)stream), "bias grad");
+}
+
+mc_status mc_nn_flip_weights_async(mc_ctx *c, const uint16_t *w, uint16_t *wt, int cout, int cin,
+                                   int cout_pad, int cin_pad, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!w || !wt || cout < 1 || cin < 1 || cout_pad < cout || cin_pad < cin)
+        return fail(c, MC_E_INVALID_ARG, "flip: bad arguments");
+    NN_RUN(c, nn_flip(w, wt, cout, cin, cout_pad, cin_pad, (hipStream_t)stream), "flip weights");
+}
+
+static mc_status resample(mc_ctx *c, int op, const uint16_t *x, int ldx, int xoff, uint16_t *y,
+                          int ldy, int yoff, int n, int h, int w, int ch, int backward,
+                          int accumulate, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!x || !y || n < 1 || h < 1 || w < 1 || ch < 1 || xoff + ch > ldx || yoff + ch > ldy ||
+        (op == 0 && (h % 2 || w % 2)))
+        return fail(c, MC_E_INVALID_ARG, "resample: bad arguments");
+    NN_RUN(c, nn_resample(op, x, ldx, xoff, y, ldy, yoff, n, h, w, ch, backward, accumulate,
+                          (hipStream_t)stream),
+           "resample");
+}
+
+mc_status mc_nn_pool2_async(mc_ctx *c, const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
+                            int yoff, int n, int h, int w, int ch, int backward, int accumulate,
+                            void *stream) {
+    return resample(c, 0, x, ldx, xoff, y, ldy, yoff, n, h, w, ch, backward, accumulate, stream);
+}
+
+mc_status mc_nn_upsample2_async(mc_ctx *c, const uint16_t *x, int ldx, int xoff, uint16_t *y,
+                                int ldy, int yoff, int n, int h, int w, int ch, int backward,
+                                int accumulate, void *stream) {
+    return resample(c, 1, x, ldx, xoff, y, ldy, yoff, n, h, w, ch, backward, accumulate, stream);
+}
+
+mc_status mc_nn_mse_async(mc_ctx *c, const float *out, int ldo, const float *target, uint64_t n,
+                          uint16_t *grad, int ldg, int goff, float gscale, float *partial,
+                          void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!out || !target || !partial || n == 0 || ldo < 1 || (grad && (goff < 0 || goff >= ldg)))
+        return fail(c, MC_E_INVALID_ARG, "mse: bad arguments");
+    NN_RUN(c, nn_mse(out, ldo, target, (int64_t)n, grad, ldg, goff, gscale, partial,
+                     (hipStream_t)stream),
+           "mse");
+}
+
+mc_status mc_nn_adam_async(mc_ctx *c, float *p, const float *g, float *m, float *v,
+                           uint16_t *pb, uint64_t n, float lr, float b1, float b2, float eps,
+                           int step, float gscale, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!p || !g || !m || !v || step < 1 || !(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f))
+        return fail(c, MC_E_INVALID_ARG, "adam: bad arguments");
+    const float c1 = (float)(1.0 - std::pow((double)b1, step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, step));
+    NN_RUN(c, nn_adam(p, g, m, v, pb, (int64_t)n, lr, b1, b2, eps, c1, c2, gscale,
+                      (hipStream_t)stream),
+           "adam");
+}
+
+mc_status mc_nn_relu_mask_async(mc_ctx *c, uint16_t *g, int ldg, int goff, const uint16_t *y,
+                                int ldy, int yoff, uint64_t npix, int ch, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!g || !y || ch < 1 || goff + ch > ldg || yoff + ch > ldy)
+        return fail(c, MC_E_INVALID_ARG, "relu mask: bad arguments");
+    NN_RUN(c, nn_relu_mask(g, ldg, goff, y, ldy, yoff, (int64_t)npix, ch, (hipStream_t)stream),
+           "relu mask");
+}
+
+mc_status mc_nn_cast_bf16_async(mc_ctx *c, const float *in, uint16_t *out, uint64_t n,
+                                void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!in || !out) return fail(c, MC_E_INVALID_ARG, "cast: null buffer");
+    NN_RUN(c, nn_cast_bf16(in, out, (int64_t)n, (hipStream_t)stream), "cast bf16");
+}
+
+mc_status mc_nn_pack_channel_async(mc_ctx *c, const float *in, uint64_t npix, float scale,
+                                   uint16_t *out, int ld, int coff, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!in || !out || coff < 0 || coff >= ld) return fail(c, MC_E_INVALID_ARG, "pack: bad arguments");
+    NN_RUN(c, nn_pack_channel(in, (int64_t)npix, scale, out, ld, coff, (hipStream_t)stream),
+           "pack channel");
 }
 
 double mc_tally_scale(void) { return 1.0 / 1048576.0; }

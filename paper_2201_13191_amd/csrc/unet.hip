@@ -1,0 +1,489 @@
+// Kernels of the learned scatter denoiser / up-sampler: a 2-D U-Net with
+// bf16 weights and activations, fp32 accumulation on the gfx950 matrix cores,
+// trained by its own backward kernels.  It stands in for the smoothing and
+// interpolation of the paper's correction loop (section II-C-3/4).
+//
+// Layout: activations NHWC bf16 ([n][y][x][c], channels fastest) addressed
+// as (pointer, channel stride ld, channel offset) so concatenated skip
+// connections are channel slices of one buffer; 3x3 conv weights bf16
+// [Cout][tap][Cin] with tap = 3*(dy+1) + (dx+1).  Channel counts of convolution
+// inputs are multiples of 16.
+//
+// conv3x3_kernel is an implicit GEMM: rows = pixels, columns = output
+// channels, reduction k = (tap, input channel).  Each lane's eight k values
+// of one MFMA operand are eight consecutive channels, a single 16-byte load
+// straight from global memory (L1/L2 serve the reuse).  One wave computes a
+// 32*WM x 32*WN tile with v_mfma_f32_32x32x16_bf16.  The same kernel computes
+// the input gradient of a convolution from its output gradient and the
+// flipped, transposed weights.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nn_params.hpp"
+
+namespace mcx {
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int WM, int WN>
+__global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int hw = a.h * a.w_;
+    const int npix = a.n * hw;
+    const int px0 = (blockIdx.x * 4 + wave) * (32 * WM);
+    const int co0 = blockIdx.y * (32 * WN);
+    if (px0 >= npix) return;
+    const int kh = lane >> 5;          // which 8-channel half of the 16-k slice
+    const int lr = lane & 31;
+
+    int pn[WM], py[WM], pxx[WM];
+    bool pv[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        const int p = px0 + i * 32 + lr;
+        pv[i] = p < npix;
+        const int pp = pv[i] ? p : 0;
+        pn[i] = pp / hw;
+        const int r = pp - pn[i] * hw;
+        py[i] = r / a.w_;
+        pxx[i] = r - py[i] * a.w_;
+    }
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const size_t wk = (size_t)9 * a.cin;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const uint16_t *xrow[WM];
+        bool inb[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const int yy = py[i] + dy, xx = pxx[i] + dx;
+            inb[i] = pv[i] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_;
+            xrow[i] = a.x + ((size_t)(pn[i] * a.h + (inb[i] ? yy : 0)) * a.w_ + (inb[i] ? xx : 0)) *
+                                a.ldx + a.xoff + kh * 8;
+        }
+        for (int c0 = 0; c0 < a.cin; c0 += 16) {
+            bf16x8 av[WM], bv[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                if (inb[i]) {
+                    av[i] = *(const bf16x8 *)(xrow[i] + c0);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) av[i][e] = 0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                const int co = co0 + j * 32 + lr;
+                bv[j] = *(const bf16x8 *)(a.w + (size_t)co * wk + (size_t)tap * a.cin + c0 + kh * 8);
+            }
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // epilogue: element r of a 32x32 accumulator is row 8*(r/4) + 4*(lane/32) + r%4,
+    // column lane%32
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const int co = co0 + j * 32 + lr;
+            if (co >= a.cout) continue;
+            const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int p = px0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (p >= npix) continue;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.mask && !(bf16_to_f32(a.mask[(size_t)p * a.ldm + a.moff + co]) > 0.0f)) v = 0.0f;
+                if (a.yf) a.yf[(size_t)p * a.cout + co] = v;
+                if (a.y) {
+                    uint16_t *dst = a.y + (size_t)p * a.ldy + a.yoff + co;
+                    if (a.accumulate) v += bf16_to_f32(*dst);
+                    *dst = f32_to_bf16(v);
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[co][tap][ci] = sum over pixels of dY[p][co] * X[p + tap][ci].
+// One block = 4 waves = a 32(co) x 32(ci) tile of one tap over a pixel range;
+// 16-pixel slices of dY and of the shifted X are staged in LDS transposed
+// (channel-major) so each lane reads its 8 consecutive pixels in one 16-byte
+// LDS load.  Per-split partial tiles are reduced in a fixed order by
+// wgrad_reduce_kernel, so gradients are deterministic.
+__global__ void __launch_bounds__(256) wgrad_kernel(const WgradArgs a) {
+    __shared__ uint16_t s_dy[4][32][16 + 8];   // [wave][co][pixel] (+8 pad)
+    __shared__ uint16_t s_x[4][32][16 + 8];    // [wave][ci][pixel]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int co0 = blockIdx.x * 32;
+    const int ci0 = (blockIdx.y % ((a.cin + 31) / 32)) * 32;
+    const int tap = blockIdx.y / ((a.cin + 31) / 32);
+    const int split = blockIdx.z;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int hw = a.h * a.w_, npix = a.n * hw;
+    const int per = (npix + a.splits - 1) / a.splits;
+    const int p_lo = split * per, p_hi = min(npix, p_lo + per);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int kh = lane >> 5, lr = lane & 31;
+    // each wave walks 16-pixel slices strided by 4 slices
+    for (int p0 = p_lo + wave * 16; p0 < p_hi; p0 += 64) {
+        // stage: lane handles pixel p0 + (lane & 15), channels 8*(lane >> 4) .. +8
+        {
+            const int pl = lane & 15, cq = lane >> 4;   // cq in 0..3: 8-channel groups
+            const int p = p0 + pl;
+            uint16_t vy[8], vx[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                vy[e] = 0;
+                vx[e] = 0;
+            }
+            if (p < p_hi) {
+                const int c = co0 + cq * 8;
+                if (c < a.cout) {
+                    const uint16_t *src = a.dy + (size_t)p * a.ldy + a.yoff + c;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) vy[e] = (c + e < a.cout) ? src[e] : (uint16_t)0;
+                }
+                const int nn = p / hw, rem = p - nn * hw, yy = rem / a.w_ + dy, xx = rem % a.w_ + dx;
+                const int ci = ci0 + cq * 8;
+                if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_ && ci < a.cin) {
+                    const bf16x8 v =
+                        *(const bf16x8 *)(a.x + ((size_t)(nn * a.h + yy) * a.w_ + xx) * a.ldx + a.xoff + ci);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) vx[e] = (uint16_t)v[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s_dy[wave][cq * 8 + e][pl] = vy[e];
+                s_x[wave][cq * 8 + e][pl] = vx[e];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);
+        bf16x8 av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            av[e] = (short)s_dy[wave][lr][kh * 8 + e];
+            bv[e] = (short)s_x[wave][lr][kh * 8 + e];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        __builtin_amdgcn_wave_barrier();
+    }
+    // reduce the 4 waves' tiles through LDS, then write this split's partial
+    __shared__ float s_acc[4][32][33];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s_acc[wave][8 * (r >> 2) + 4 * kh + (r & 3)][lr] = acc[r];
+    __syncthreads();
+    for (int t = threadIdx.x; t < 32 * 32; t += 256) {
+        const int row = t >> 5, col = t & 31;
+        const float s = ((s_acc[0][row][col] + s_acc[1][row][col]) + s_acc[2][row][col]) +
+                        s_acc[3][row][col];
+        const int co = co0 + row, ci = ci0 + col;
+        if (co < a.cout && ci < a.cin)
+            a.partial[(((size_t)split * 9 + tap) * a.cout + co) * a.cin + ci] = s;
+    }
+}
+
+// dW[co][tap][ci] = sum over splits in order (fp32), optionally + bias grads
+__global__ void wgrad_reduce_kernel(const float *partial, int splits, int n, float *dw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // partial is [split][tap][co][ci]; dw is [co][tap][ci] with n = 9*cout*cin
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * n + i];
+    dw[i] = s;
+}
+
+// [tap][co][ci] -> [co][tap][ci]
+__global__ void wgrad_permute_kernel(const float *t, float *dw, int cout, int cin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 9 * cout * cin;
+    if (i >= n) return;
+    const int ci = i % cin, co = (i / cin) % cout, tap = i / (cin * cout);
+    dw[((size_t)co * 9 + tap) * cin + ci] = t[i];
+}
+
+// bias gradient: db[c] = sum over pixels of dy[p][c], per-block partials then a
+// fixed-order sum
+__global__ void colsum_kernel(const uint16_t *dy, int ldy, int yoff, int npix, int c, int chunk,
+                              float *partial) {
+    const int ch = blockIdx.y * blockDim.x + threadIdx.x;
+    if (ch >= c) return;
+    const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    float s = 0.0f;
+    for (int p = p0; p < p1; ++p) s += bf16_to_f32(dy[(size_t)p * ldy + yoff + ch]);
+    partial[(size_t)blockIdx.x * c + ch] = s;
+}
+
+__global__ void rowsum_kernel(const float *partial, int rows, int c, float *out) {
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= c) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += partial[(size_t)r * c + ch];
+    out[ch] = s;
+}
+
+// W'[ci][tap][co] = W[co][8 - tap][ci] (bf16): weights of the input-gradient
+// convolution; columns co >= cout and rows ci >= cin are zero padding
+__global__ void flip_weights_kernel(const uint16_t *w, uint16_t *wt, int cout, int cin,
+                                    int cout_pad, int cin_pad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = cin_pad * 9 * cout_pad;
+    if (i >= n) return;
+    const int co = i % cout_pad, tap = (i / cout_pad) % 9, ci = i / (9 * cout_pad);
+    uint16_t v = 0;
+    if (co < cout && ci < cin) v = w[((size_t)co * 9 + (8 - tap)) * cin + ci];
+    wt[i] = v;
+}
+
+// 2x2 average pooling and its gradient; nearest 2x up-sampling and its gradient
+__global__ void pool2_kernel(const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy, int yoff,
+                             int n, int h, int w, int c, int backward, int accumulate) {
+    // forward: y[n][h/2][w/2] from x[n][h][w]; backward: x-shaped gradient (here x
+    // is dy at the pooled size, y the full-size gradient)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!backward) {
+        const int ho = h / 2, wo = w / 2;
+        const int64_t total = (int64_t)n * ho * wo * c;
+        if (i >= total) return;
+        const int ch = (int)(i % c);
+        const int64_t q = i / c;
+        const int xo = (int)(q % wo), yo = (int)((q / wo) % ho), nn = (int)(q / ((int64_t)wo * ho));
+        float s = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int yy = 2 * yo + (t >> 1), xx = 2 * xo + (t & 1);
+            s += bf16_to_f32(x[((size_t)(nn * h + yy) * w + xx) * ldx + xoff + ch]);
+        }
+        uint16_t *dst = y + ((size_t)(nn * ho + yo) * wo + xo) * ldy + yoff + ch;
+        float v = 0.25f * s;
+        if (accumulate) v += bf16_to_f32(*dst);
+        *dst = f32_to_bf16(v);
+    } else {
+        const int64_t total = (int64_t)n * h * w * c;
+        if (i >= total) return;
+        const int ch = (int)(i % c);
+        const int64_t q = i / c;
+        const int xx = (int)(q % w), yy = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+        const int ho = h / 2, wo = w / 2;
+        float v = 0.25f * bf16_to_f32(x[((size_t)(nn * ho + yy / 2) * wo + xx / 2) * ldx + xoff + ch]);
+        uint16_t *dst = y + ((size_t)(nn * h + yy) * w + xx) * ldy + yoff + ch;
+        if (accumulate) v += bf16_to_f32(*dst);
+        *dst = f32_to_bf16(v);
+    }
+}
+
+__global__ void up2_kernel(const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy, int yoff,
+                           int n, int h, int w, int c, int backward, int accumulate) {
+    // forward: y[n][2h][2w] = x[n][h][w]; backward: y[n][h][w] = sum of the 4 children
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!backward) {
+        const int64_t total = (int64_t)n * 2 * h * 2 * w * c;
+        if (i >= total) return;
+        const int ch = (int)(i % c);
+        const int64_t q = i / c;
+        const int xx = (int)(q % (2 * w)), yy = (int)((q / (2 * w)) % (2 * h)),
+                  nn = (int)(q / ((int64_t)4 * w * h));
+        float v = bf16_to_f32(x[((size_t)(nn * h + yy / 2) * w + xx / 2) * ldx + xoff + ch]);
+        uint16_t *dst = y + ((size_t)(nn * 2 * h + yy) * 2 * w + xx) * ldy + yoff + ch;
+        if (accumulate) v += bf16_to_f32(*dst);
+        *dst = f32_to_bf16(v);
+    } else {
+        const int64_t total = (int64_t)n * h * w * c;
+        if (i >= total) return;
+        const int ch = (int)(i % c);
+        const int64_t q = i / c;
+        const int xo = (int)(q % w), yo = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+        float s = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int yy = 2 * yo + (t >> 1), xx = 2 * xo + (t & 1);
+            s += bf16_to_f32(x[((size_t)(nn * 2 * h + yy) * 2 * w + xx) * ldx + xoff + ch]);
+        }
+        uint16_t *dst = y + ((size_t)(nn * h + yo) * w + xo) * ldy + yoff + ch;
+        if (accumulate) s += bf16_to_f32(*dst);
+        *dst = f32_to_bf16(s);
+    }
+}
+
+// loss = sum (out - t)^2 / n over fp32 maps (per-block partials, fixed order);
+// gradient 2 (out - t) / n * scale written as bf16 into channel `goff` of an
+// NHWC buffer with channel stride ldg (other channels untouched)
+__global__ void mse_kernel(const float *out, int ldo, const float *t, int64_t n, uint16_t *g,
+                           int ldg, int goff, float gscale, float *partial) {
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float d = 0.0f;
+    if (i < n) {
+        d = out[(size_t)i * ldo] - t[i];
+        if (g) g[(size_t)i * ldg + goff] = f32_to_bf16(2.0f * d / (float)n * gscale);
+    }
+    red[threadIdx.x] = d * d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Adam on fp32 master weights; writes the bf16 copy the forward pass reads
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n,
+                            float lr, float b1, float b2, float eps, float c1, float c2,
+                            float gscale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] * gscale;
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f32_to_bf16(pi);
+}
+
+// g[p][c] = 0 where y[p][c] <= 0: gradient through a ReLU whose output is y
+__global__ void relu_mask_kernel(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy,
+                                 int yoff, int64_t npix, int c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * c) return;
+    const int64_t p = i / c;
+    const int ch = (int)(i - p * c);
+    if (!(bf16_to_f32(y[(size_t)p * ldy + yoff + ch]) > 0.0f)) g[(size_t)p * ldg + goff + ch] = 0;
+}
+
+__global__ void cast_bf16_kernel(const float *in, uint16_t *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = f32_to_bf16(in[i]);
+}
+
+// fp32 planes [n][h][w] -> channel `coff` of an NHWC bf16 buffer (scaled)
+__global__ void pack_channel_kernel(const float *in, int64_t npix, float scale, uint16_t *out,
+                                    int ld, int coff) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npix) out[(size_t)i * ld + coff] = f32_to_bf16(in[i] * scale);
+}
+
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t nn_conv3x3(const ConvArgs &a, hipStream_t s) {
+    const int npix = a.n * a.h * a.w_;
+    if (a.cout <= 32) {
+        const dim3 grid((npix + 4 * 64 - 1) / (4 * 64), (a.cout + 31) / 32);
+        hipLaunchKernelGGL((conv3x3_kernel<2, 1>), grid, dim3(256), 0, s, a);
+    } else {
+        const dim3 grid((npix + 4 * 64 - 1) / (4 * 64), (a.cout + 63) / 64);
+        hipLaunchKernelGGL((conv3x3_kernel<2, 2>), grid, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t nn_wgrad(const WgradArgs &a, float *tmp, float *dw, hipStream_t s) {
+    const dim3 grid((a.cout + 31) / 32, 9 * ((a.cin + 31) / 32), a.splits);
+    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, a);
+    const int n = 9 * a.cout * a.cin;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                       (const float *)a.partial, a.splits, n, tmp);
+    hipLaunchKernelGGL(wgrad_permute_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                       (const float *)tmp, dw, a.cout, a.cin);
+    return hipGetLastError();
+}
+
+hipError_t nn_colsum(const uint16_t *dy, int ldy, int yoff, int npix, int c, float *partial,
+                     int rows, float *out, hipStream_t s) {
+    const int chunk = (npix + rows - 1) / rows;
+    hipLaunchKernelGGL(colsum_kernel, dim3(rows, (c + 63) / 64), dim3(64), 0, s, dy, ldy, yoff,
+                       npix, c, chunk, partial);
+    hipLaunchKernelGGL(rowsum_kernel, dim3((c + 63) / 64), dim3(64), 0, s, (const float *)partial,
+                       rows, c, out);
+    return hipGetLastError();
+}
+
+hipError_t nn_flip(const uint16_t *w, uint16_t *wt, int cout, int cin, int cout_pad, int cin_pad,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(blocks_for((int64_t)cin_pad * 9 * cout_pad)),
+                       dim3(256), 0, s, w, wt, cout, cin, cout_pad, cin_pad);
+    return hipGetLastError();
+}
+
+hipError_t nn_resample(int op, const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
+                       int yoff, int n, int h, int w, int c, int backward, int accumulate,
+                       hipStream_t s) {
+    int64_t total;
+    if (op == 0) total = backward ? (int64_t)n * h * w * c : (int64_t)n * (h / 2) * (w / 2) * c;
+    else total = backward ? (int64_t)n * h * w * c : (int64_t)n * 4 * h * w * c;
+    if (op == 0)
+        hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(total)), dim3(256), 0, s, x, ldx, xoff, y,
+                           ldy, yoff, n, h, w, c, backward, accumulate);
+    else
+        hipLaunchKernelGGL(up2_kernel, dim3(blocks_for(total)), dim3(256), 0, s, x, ldx, xoff, y,
+                           ldy, yoff, n, h, w, c, backward, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t nn_mse(const float *out, int ldo, const float *t, int64_t n, uint16_t *g, int ldg,
+                  int goff, float gscale, float *partial, hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(blocks_for(n)), dim3(256), 0, s, out, ldo, t, n, g, ldg,
+                       goff, gscale, partial);
+    return hipGetLastError();
+}
+
+hipError_t nn_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr,
+                   float b1, float b2, float eps, float c1, float c2, float gscale, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, g, m, v, pb, n, lr,
+                       b1, b2, eps, c1, c2, gscale);
+    return hipGetLastError();
+}
+
+hipError_t nn_relu_mask(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy, int yoff,
+                        int64_t npix, int c, hipStream_t s) {
+    hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c)), dim3(256), 0, s, g, ldg, goff,
+                       y, ldy, yoff, npix, c);
+    return hipGetLastError();
+}
+
+hipError_t nn_cast_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(cast_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_pack_channel(const float *in, int64_t npix, float scale, uint16_t *out, int ld,
+                           int coff, hipStream_t s) {
+    hipLaunchKernelGGL(pack_channel_kernel, dim3(blocks_for(npix)), dim3(256), 0, s, in, npix,
+                       scale, out, ld, coff);
+    return hipGetLastError();
+}
+
+}  // namespace mcx

@@ -28,7 +28,10 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_set_stats", "mc_get_stats", "mc_get_tables", "mc_set_layout", "mc_get_layout",
            "mc_set_launch", "mc_tally_scale", "mc_phantom_add", "mc_project_batch",
            "mc_get_shape", "mc_autotune", "mc_tally_to_float_async", "mc_savgol_async",
-           "mc_upsample_cubic_async", "mc_savgol_weights"]
+           "mc_upsample_cubic_async", "mc_savgol_weights", "mc_nn_conv3x3_async",
+           "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
+           "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
+           "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -56,6 +59,14 @@ class mc_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("event_batch", C.c_int32),
                 ("from_cache", C.c_int32), ("candidates", C.c_int32), ("rejected", C.c_int32),
                 ("ms", C.c_double), ("histories_per_s", C.c_double)]
+
+
+class mc_conv3x3(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("ldx", C.c_int32), ("xoff", C.c_int32), ("w", C.c_void_p),
+                ("bias", C.c_void_p), ("y", C.c_void_p), ("ldy", C.c_int32), ("yoff", C.c_int32),
+                ("yf", C.c_void_p), ("mask", C.c_void_p), ("ldm", C.c_int32), ("moff", C.c_int32),
+                ("n", C.c_int32), ("h", C.c_int32), ("w_", C.c_int32), ("cin", C.c_int32),
+                ("cout", C.c_int32), ("relu", C.c_int32), ("accumulate", C.c_int32)]
 
 
 class mc_stats(C.Structure):
@@ -110,6 +121,17 @@ def load():
         "mc_savgol_async": ([P, P, P, P, I, I, I, I, P], I),
         "mc_upsample_cubic_async": ([P, P, P, I, I, I, P], I),
         "mc_savgol_weights": ([I, I, P], I),
+        "mc_nn_conv3x3_async": ([P, C.POINTER(mc_conv3x3), P], I),
+        "mc_nn_conv3x3_wgrad_async": ([P, P, I, I, P, I, I, I, I, I, I, I, I, P, P, P], I),
+        "mc_nn_bias_grad_async": ([P, P, I, I, I, I, P, I, P, P], I),
+        "mc_nn_flip_weights_async": ([P, P, P, I, I, I, I, P], I),
+        "mc_nn_pool2_async": ([P, P, I, I, P, I, I, I, I, I, I, I, I, P], I),
+        "mc_nn_upsample2_async": ([P, P, I, I, P, I, I, I, I, I, I, I, I, P], I),
+        "mc_nn_mse_async": ([P, P, I, P, U64, P, I, I, F, P, P], I),
+        "mc_nn_adam_async": ([P, P, P, P, P, P, U64, F, F, F, F, I, F, P], I),
+        "mc_nn_relu_mask_async": ([P, P, I, I, P, I, I, U64, I, P], I),
+        "mc_nn_cast_bf16_async": ([P, P, P, U64, P], I),
+        "mc_nn_pack_channel_async": ([P, P, U64, F, P, I, I, P], I),
         "mc_autotune": ([P, F, U64, U64, C.c_char_p, C.POINTER(mc_tuning)], I),
     }
     for name, (args, res) in sig.items():
@@ -318,6 +340,70 @@ def mc_savgol_weights(window, order):
     if rc:
         raise MCXError(rc, "bad window/order")
     return w
+
+
+def _p(t):
+    return None if t is None else (t if isinstance(t, int) else t.data_ptr())
+
+
+def mc_nn_conv3x3_async(ctx, x, ldx, xoff, w, bias, y, ldy, yoff, n, h, w_, cin, cout, relu=0,
+                        yf=None, mask=None, ldm=0, moff=0, accumulate=0, stream=None):
+    a = mc_conv3x3(_p(x), ldx, xoff, _p(w), _p(bias), _p(y), ldy, yoff, _p(yf), _p(mask), ldm,
+                   moff, n, h, w_, cin, cout, int(relu), int(accumulate))
+    _check(ctx, load().mc_nn_conv3x3_async(ctx, C.byref(a), _stream(stream)))
+
+
+def mc_nn_conv3x3_wgrad_async(ctx, x, ldx, xoff, dy, ldy, yoff, n, h, w, cin, cout, splits,
+                              workspace, dw, stream=None):
+    _check(ctx, load().mc_nn_conv3x3_wgrad_async(ctx, _p(x), ldx, xoff, _p(dy), ldy, yoff, n, h,
+                                                 w, cin, cout, splits, _p(workspace), _p(dw),
+                                                 _stream(stream)))
+
+
+def mc_nn_bias_grad_async(ctx, dy, ldy, yoff, npix, c, workspace, rows, db, stream=None):
+    _check(ctx, load().mc_nn_bias_grad_async(ctx, _p(dy), ldy, yoff, npix, c, _p(workspace), rows,
+                                             _p(db), _stream(stream)))
+
+
+def mc_nn_flip_weights_async(ctx, w, wt, cout, cin, cout_pad, cin_pad, stream=None):
+    _check(ctx, load().mc_nn_flip_weights_async(ctx, _p(w), _p(wt), cout, cin, cout_pad, cin_pad,
+                                                _stream(stream)))
+
+
+def mc_nn_pool2_async(ctx, x, ldx, xoff, y, ldy, yoff, n, h, w, c, backward=0, accumulate=0,
+                      stream=None):
+    _check(ctx, load().mc_nn_pool2_async(ctx, _p(x), ldx, xoff, _p(y), ldy, yoff, n, h, w, c,
+                                         int(backward), int(accumulate), _stream(stream)))
+
+
+def mc_nn_upsample2_async(ctx, x, ldx, xoff, y, ldy, yoff, n, h, w, c, backward=0, accumulate=0,
+                          stream=None):
+    _check(ctx, load().mc_nn_upsample2_async(ctx, _p(x), ldx, xoff, _p(y), ldy, yoff, n, h, w, c,
+                                             int(backward), int(accumulate), _stream(stream)))
+
+
+def mc_nn_mse_async(ctx, out, ldo, target, n, grad, ldg, goff, gscale, partial, stream=None):
+    _check(ctx, load().mc_nn_mse_async(ctx, _p(out), ldo, _p(target), n, _p(grad), ldg, goff,
+                                       gscale, _p(partial), _stream(stream)))
+
+
+def mc_nn_adam_async(ctx, p, g, m, v, pb, n, lr, b1, b2, eps, step, gscale=1.0, stream=None):
+    _check(ctx, load().mc_nn_adam_async(ctx, _p(p), _p(g), _p(m), _p(v), _p(pb), n, lr, b1, b2,
+                                        eps, step, gscale, _stream(stream)))
+
+
+def mc_nn_relu_mask_async(ctx, g, ldg, goff, y, ldy, yoff, npix, c, stream=None):
+    _check(ctx, load().mc_nn_relu_mask_async(ctx, _p(g), ldg, goff, _p(y), ldy, yoff, npix, c,
+                                             _stream(stream)))
+
+
+def mc_nn_cast_bf16_async(ctx, x, out, n, stream=None):
+    _check(ctx, load().mc_nn_cast_bf16_async(ctx, _p(x), _p(out), n, _stream(stream)))
+
+
+def mc_nn_pack_channel_async(ctx, x, npix, scale, out, ld, coff, stream=None):
+    _check(ctx, load().mc_nn_pack_channel_async(ctx, _p(x), npix, scale, _p(out), ld, coff,
+                                                _stream(stream)))
 
 
 def mc_tally_scale():
