@@ -587,33 +587,37 @@ typedef struct {
     uint8_t end, first;
 } hist_t;
 
-/* Fixed-step march from entry t_in to exit t_out.  Step k covers
- * [k*step, min((k+1)*step, L)) of the chord (the last step clipped); the
- * voxel at the step midpoint gives mu; the photon interacts in the first step
- * where the accumulated optical depth reaches tau_star, at the linearly
- * interpolated point.  Returns 1 with the interaction point and voxel. */
+/* Fixed-step march from entry t_in to exit t_out (section II-C-2 fixes only
+ * that the step size is a free parameter; this discretisation is the one
+ * both implementations follow).  L = t_out - t_in.  Step k starts at
+ * a_k = k*step (one fp32 product) and is taken while a_k < L; it has length
+ * step, except the last one (the first k with (k+1)*step >= L), whose length
+ * is L - a_k.  Its voxel contains the step's nominal centre (k + 1/2)*step,
+ * kept in voxel coordinates and advanced by repeated addition:
+ * c_0 = (p_in - lo)/h + G/2 and c_{k+1} = c_k + G with G = (d/h)*step,
+ * truncated and clamped to the object.  The photon interacts in the first
+ * step where the accumulated optical depth reaches tau_star, at the linearly
+ * interpolated point a_k + (tau_star - tau)/mu.  Returns 1 with the
+ * interaction point and voxel. */
 static int march(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
                  float tin, float tout, const float *mm, float tau_star, float pint[3],
                  size_t *vox, uint32_t *steps) {
-    float pin[3], q[3], e[3];
+    const float dl = c->g.step_mm;
+    float pin[3], q[3], G[3];
     for (int a = 0; a < 3; ++a) pin[a] = p[a] + d[a] * tin;
     float L = tout - tin;
     for (int a = 0; a < 3; ++a) {
-        q[a] = (pin[a] - P->lo[a]) * P->inv_h;
-        e[a] = d[a] * P->inv_h;
+        G[a] = (d[a] * P->inv_h) * dl;
+        q[a] = (pin[a] - P->lo[a]) * P->inv_h + 0.5f * G[a];
     }
-    const float dl = c->g.step_mm;
     float tau = 0.0f;
     for (uint32_t k = 0;; ++k) {
         float a0 = (float)k * dl;
         if (!(a0 < L)) return 0;
-        float b = a0 + dl;
-        if (b > L) b = L;
-        float dk = b - a0;
-        float s = 0.5f * (a0 + b);
-        int ix = (int)(q[0] + e[0] * s);
-        int iy = (int)(q[1] + e[1] * s);
-        int iz = (int)(q[2] + e[2] * s);
+        float dk = ((float)(k + 1u) * dl < L) ? dl : L - a0;
+        int ix = (int)q[0];
+        int iy = (int)q[1];
+        int iz = (int)q[2];
         ix = ix < 0 ? 0 : (ix > c->nx - 1 ? c->nx - 1 : ix);
         iy = iy < 0 ? 0 : (iy > c->ny - 1 ? c->ny - 1 : iy);
         iz = iz < 0 ? 0 : (iz > c->nz - 1 ? c->nz - 1 : iz);
@@ -629,6 +633,7 @@ static int march(const mco_ctx *c, const proj_t *P, const float p[3], const floa
             return 1;
         }
         tau = tnext;
+        for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
     }
 }
 

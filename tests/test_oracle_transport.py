@@ -155,7 +155,8 @@ def test_detector_pencil_rays(oracle_lib):
 def fixed_step_tau(ids, rho, h, mm, p, d, step):
     """Independent fp64 fixed-step optical depth along each ray (p, d are
     [n,3]): entry/exit of the box, steps of `step` with the last one clipped,
-    material looked up at each step midpoint."""
+    material looked up at each step's nominal centre (k + 1/2) * step,
+    clamped to the object."""
     n = np.array(ids.shape[::-1], np.float64)            # nx, ny, nz
     lo, hi = -n * h / 2, n * h / 2
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -169,7 +170,7 @@ def fixed_step_tau(ids, rho, h, mm, p, d, step):
         a = k * step
         live = a < L
         b = np.minimum(a + step, L)
-        s = tin + 0.5 * (a + b)
+        s = tin + a + 0.5 * step
         m = p + d * s[:, None]
         idx = np.clip(np.floor((m - lo) / h).astype(np.int64), 0, n.astype(np.int64) - 1)
         mu = rho[idx[:, 2], idx[:, 1], idx[:, 0]] * mm[ids[idx[:, 2], idx[:, 1], idx[:, 0]]]
