@@ -27,10 +27,11 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 # 32-bit VALU issue peak (non-packed): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # arithmetic of one fixed-step march step as the transport specifies it:
-# step start and clipped end (4), step length and midpoint (3), voxel
-# coordinates (6), clamped indices (6), voxel address (4), optical depth and
-# the two tests (4), step advance (1)
-ALU_OPS_PER_STEP = 28
+# advance of the step centre (3 adds), clamp (3) and truncation (3) of the
+# voxel coordinates, linear voxel index (2 multiplies, 2 adds), end-of-chord
+# test and last-step length selection (2), optical depth (multiply, add) and
+# its test against tau* (1)
+ALU_OPS_PER_STEP = 18
 TALLY_BYTES = 8                  # one int64 atomic add per detected photon
 COUNTERS = os.path.join(ROOT, "profiles", "transport_ellipsoids256_poly_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2201_13191_amd", "csrc", f)
@@ -82,6 +83,74 @@ def cpu_baseline(w, seconds):
                        f"one step), {dt:.1f} s wall on {threads} host threads")
 
 
+def bench_batch(args):
+    """Batched persistent launch (hipGraph replay) over the batch workload:
+    360 angles of the 256^3 object plus 16 objects of uneven size."""
+    import torch
+    from paper_2201_13191_amd import inputs, mcx
+    log("generating batch workload")
+    w = inputs.batch_workload()
+    g = mcx.Projector(0)
+    g.load_phantom(*w["phantoms"][0])
+    handles = [0] + [mcx.mc_phantom_add(g.ctx, ids, rho, h) for ids, rho, h in w["phantoms"][1:]]
+    g.set_geometry(**w["geometry"])
+    g.set_spectrum(*w["spectrum"])
+    geo = w["geometry"]
+    per = geo["nu"] * geo["nv"] + geo["snu"] * geo["snv"]
+    jobs = [dict(j, phantom=handles[j["phantom"]], primary_offset=i * per,
+                 scatter_offset=i * per + geo["nu"] * geo["nv"]) for i, j in enumerate(w["jobs"])]
+    out_buf = torch.empty(len(jobs) * per, dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    n = sum(j["n_photons"] for j in jobs)
+
+    def step():
+        mcx.mc_project_batch(g.ctx, jobs, out_buf, out_buf.numel(), flags=mcx.MC_BATCH_GRAPH,
+                             stream=stream)
+
+    log("counting pass")
+    g.stats(True)
+    mcx.mc_project_batch(g.ctx, jobs, out_buf, out_buf.numel(), flags=0, stream=stream)
+    torch.cuda.synchronize()
+    st = g.stats()
+    g.stats(False)
+    alg_ops = st["steps"] * ALU_OPS_PER_STEP
+    alg_bytes = st["steps"] + (st["primary_hits"] + st["scatter_hits"]) * TALLY_BYTES
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e-3
+    achieved = alg_ops / launch_s / 1e12
+    out = {
+        "metric": "photon histories/s on 1 GPU (batched persistent launch, hipGraph)",
+        "value": n * args.steps / wall, "unit": "photon histories/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "jobs": len(jobs), "photons_per_step": n,
+                   "objects": "256^3 (360 angles x 1e7) + 16 objects 64^3..384^3 at 0.5 mm",
+                   "detector": f"{geo['nu']}x{geo['nv']} at {geo['pu_mm']} mm"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "T op/s", "frac": achieved / (VALU_PEAK_OPS / 1e12),
+                     "traffic": None, "kernel": "transport_kernel (batch)",
+                     "algorithmic_ops_per_launch": alg_ops, "ops_per_step": ALU_OPS_PER_STEP,
+                     "launch_ms": launch_s * 1e3,
+                     "gather": {"algorithmic_bytes_per_launch": alg_bytes,
+                                "achieved_GBs": alg_bytes / launch_s / 1e9}},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +184,9 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
         return
 
+    if args.workload == "batch360_uneven16":
+        bench_batch(args)
+        return
     log("generating workload", args.workload)
     w = inputs.workload(args.workload)
     n = args.photons or w["n_photons"]

@@ -41,7 +41,8 @@ struct VoxelGrid {
     int layout;                // Layout of this object
     int nx, ny, nz;
     int nbx, nby;              // bricks along x and y
-    uint32_t sy, sz;           // byte strides of one brick row (y) and one brick slab (z)
+    uint32_t ry, rz;           // byte strides of one brick row (y) and one brick slab (z),
+                               // less 32 and 128: the parts 8*iy and 32*iz already count
     float cmax[3];             // nx - 1, ny - 1, nz - 1 as floats (voxel-coordinate clamp)
     float inv_h;
     float lo[3], hi[3];

@@ -282,8 +282,8 @@ VoxelGrid grid_of(const mc_ctx *c, const Phantom &ph) {
     G.layout = phantom_layout(c, ph);
     G.nx = ph.nx; G.ny = ph.ny; G.nz = ph.nz;
     G.nbx = ph.nbx; G.nby = ph.nby;
-    G.sy = (uint32_t)ph.nbx * kBrick;
-    G.sz = (uint32_t)ph.nbx * ph.nby * kBrick;
+    G.ry = (uint32_t)ph.nbx * kBrick - 32u;
+    G.rz = (uint32_t)ph.nbx * ph.nby * kBrick - 128u;
     G.cmax[0] = (float)(ph.nx - 1);
     G.cmax[1] = (float)(ph.ny - 1);
     G.cmax[2] = (float)(ph.nz - 1);
@@ -473,6 +473,9 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     const size_t nv = (size_t)nx * ny * nz;
     const size_t padded = (size_t)nbx * nby * nbz * kBrick;
     if (padded >= (size_t)1 << 31) return fail(c, MC_E_INVALID_ARG, "phantom too large (2^31 voxels)");
+    // the kernel multiplies brick strides in 24 bits
+    if ((size_t)nbx * nby * kBrick - kBrick >= ((size_t)1 << 24))
+        return fail(c, MC_E_INVALID_ARG, "phantom too large (an x-y slab of bricks above 16 MiB)");
     // validate and collect the distinct (id, density) pairs, first appearance first
     int max_id = 0;
     uint32_t pal_rho_bits[256];

@@ -224,13 +224,27 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// byte offset of voxel (ix, iy, iz) in the bricked arrays: brick slab and
-// row strides times brick indices (24-bit multiplies; brick indices are
-// below 2^10), plus the brick column and the position inside the brick
+// byte offset of voxel (ix, iy, iz) in the bricked arrays,
+//   (iz>>2)*slab + (iy>>2)*row + (ix>>3)*128 + (iz&3)*32 + (iy&3)*8 + (ix&7),
+// regrouped as ix + 120*(ix>>3) + 8*iy + (row-32)*(iy>>2) + 32*iz + (slab-128)*(iz>>2)
+// so that each axis costs one shift and one 24-bit multiply-add (the runtime
+// keeps row-32 and slab-128 below 2^24)
 __device__ __forceinline__ uint32_t brick_offset(const VoxelGrid &p, uint32_t ix, uint32_t iy,
                                                  uint32_t iz) {
-    const uint32_t b = __umul24(iz >> 2, p.sz) + __umul24(iy >> 2, p.sy) + ((ix >> 3) << 7);
-    return b | ((iz & 3u) << 5) | ((iy & 3u) << 3) | (ix & 7u);
+    uint32_t o = __umul24(ix >> 3, 120u) + ix;
+    o += __umul24(iy >> 2, p.ry) + (iy << 3);
+    o += __umul24(iz >> 2, p.rz) + (iz << 5);
+    return o;
+}
+
+// number of march steps of a chord of length len: the count of k >= 0 with
+// (float)k * step < len (an increasing sequence), from the quotient's estimate
+__device__ __forceinline__ uint32_t step_count(float len, float step) {
+    if (!(len > 0.0f)) return 0u;
+    uint32_t n = (uint32_t)(len / step);
+    while (n > 0u && !((float)(n - 1u) * step < len)) --n;
+    while ((float)n * step < len) ++n;
+    return n;
 }
 
 // voxel index along one axis: truncation of the voxel coordinate clamped to
@@ -253,6 +267,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     const int bs = blockDim.x;
     float *mm = lds + kLdsHeader + threadIdx.x;
     float *mu_pal = mm + p.n_mat * bs;
+    const uint32_t bs4 = (uint32_t)bs * 4u;   // byte stride between a lane's LDS entries
     const int lane = (int)__lane_id();
     if (!BATCH && MODE != kGeneric) {
         for (int i = threadIdx.x; i < p.G.n_pal; i += bs) {
@@ -273,9 +288,9 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     uint64_t pid = 0;
     float e = 0.0f;
     float o[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
-    float q[3], g[3];
-    float tin = 0.0f, len = 0.0f, tau = 0.0f, tau_star = 0.0f;
-    uint32_t k = 0;
+    float q[3], G[3];
+    float tin = 0.0f, last = 0.0f, tau = 0.0f, tau_star = 0.0f;
+    uint32_t k = 0, nsteps = 0;
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
@@ -440,13 +455,17 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             float tout;
             if (box_entry(gl, o, d, tin, tout)) {
                 tau_star = (float)(-log((double)rng.u()));
+                // voxel coordinates of the first step's nominal centre and the
+                // per-step increment; the step count and the last step's length
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const float pin = o[a] + d[a] * tin;
-                    q[a] = (pin - gl.lo[a]) * gl.inv_h;
-                    g[a] = d[a] * gl.inv_h;
+                    G[a] = (d[a] * gl.inv_h) * p.step;
+                    q[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
                 }
-                len = tout - tin;
+                const float len = tout - tin;
+                nsteps = step_count(len, p.step);
+                last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
                 tau = 0.0f;
                 k = 0;
                 flying = true;
@@ -456,31 +475,30 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             }
         }
         // ---- 5. march until `event_batch` lanes wait for an event (or none flies).
-        //         Each group issues the voxel loads of kPrefetch consecutive steps,
-        //         then consumes them in order without branches: tau and the step
-        //         index advance by selection, the step that reaches tau* is recorded,
-        //         and the interaction point is computed once after the group.
+        //         Each group issues the voxel loads of kPrefetch consecutive steps
+        //         (advancing the step centre by repeated addition), then consumes
+        //         them in order without branches: tau and the step index advance by
+        //         selection, the step that reaches tau* is recorded, and the
+        //         interaction point is computed once after the group.  A lane whose
+        //         flight ends inside the group no longer needs its step centre.
         for (;;) {
             if (!__any(flying)) break;
             if (__popcll(__ballot(alive && !flying)) >= (unsigned)p.event_batch) break;
             if (!flying) continue;
             uint32_t code[kPrefetch];
-            float vr[kPrefetch], a0v[kPrefetch], dkv[kPrefetch];
+            float vr[kPrefetch];
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
-                const float a0 = (float)(k + u) * p.step;
-                float b = a0 + p.step;
-                if (b > len) b = len;
-                a0v[u] = a0;
-                dkv[u] = b - a0;
-                const float s = 0.5f * (a0 + b);
-                const uint32_t ix = voxel_index(q[0] + g[0] * s, gl.cmax[0]);
-                const uint32_t iy = voxel_index(q[1] + g[1] * s, gl.cmax[1]);
-                const uint32_t iz = voxel_index(q[2] + g[2] * s, gl.cmax[2]);
+                const uint32_t ix = voxel_index(q[0], gl.cmax[0]);
+                const uint32_t iy = voxel_index(q[1], gl.cmax[1]);
+                const uint32_t iz = voxel_index(q[2], gl.cmax[2]);
                 const uint32_t off = brick_offset(gl, ix, iy, iz);
                 code[u] = gl.vox[off];
                 if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
             }
+            const uint32_t rem = nsteps - k;   // steps left in this flight
             const int lay = BATCH ? gl.layout : MODE;
             bool act = true, hit = false, out = false;
             float mu_hit = 1.0f;
@@ -488,15 +506,16 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
                 float mu;
-                if (lay == kPaletteLane)
-                    mu = mu_pal[code[u] * bs];
+                if (lay == kPaletteLane)   // one 24-bit multiply-add for the LDS address
+                    mu = *(const float *)((const char *)mu_pal + __umul24(code[u], bs4));
                 else if (lay == kPaletteShared)
                     mu = BATCH ? gl.pal_rho[code[u]] * mm[gl.pal_id[code[u]] * bs]
                                : s_pal_rho[code[u]] * mm[s_pal_id[code[u]] * bs];
                 else
                     mu = vr[u] * mm[code[u] * bs];
-                const bool inside = a0v[u] < len;
-                const float tn = tau + mu * dkv[u];
+                const bool inside = (uint32_t)u < rem;
+                const float dk = (uint32_t)(u + 1) == rem ? last : p.step;
+                const float tn = tau + mu * dk;
                 const bool step = act && inside;
                 const bool reach = step && (tn >= tau_star);
                 if (DEBUG) h_steps += step ? 1u : 0u;

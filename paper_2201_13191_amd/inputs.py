@@ -154,3 +154,27 @@ def workload(name: str):
                     spectrum=kramers_spectrum(150, 2.0), n_photons=1_000_000_000, seed=0,
                     angle=0.0)
     raise KeyError(name)
+
+
+def batch_workload():
+    """Batched launch: 360 angles x 1e7 photons of the 256^3 benchmark object,
+    plus 16 random-ellipsoid objects of uneven size (64^3 .. 384^3 at 0.5 mm,
+    one projection each at a random angle, 1e6 .. 5e7 photons log-uniform).
+    Geometry and spectrum of the benchmark.  Returns dict with phantoms (list
+    of (ids, rho, voxel_mm)), jobs (list of dicts: phantom, angle_rad,
+    n_photons, seed), geometry, spectrum."""
+    base = workload("ellipsoids256_poly")
+    phantoms = [(base["ids"], base["rho"], base["voxel_mm"])]
+    rng = np.random.Generator(np.random.Philox(360))
+    sizes = [int(round(v / 8.0)) * 8 for v in np.linspace(64, 384, 16)]
+    jobs = [dict(phantom=0, angle_rad=float(np.float32(2.0 * np.pi * k / 360.0)),
+                 n_photons=10_000_000, seed=1000 + k) for k in range(360)]
+    for i, n in enumerate(sizes):
+        ids, rho = ellipsoid_phantom(n, 0.5, seed=100 + i)
+        phantoms.append((ids, rho, 0.5))
+        jobs.append(dict(phantom=i + 1, angle_rad=float(np.float32(rng.uniform(0, 2 * np.pi))),
+                         n_photons=int(round(10 ** rng.uniform(6.0, np.log10(5e7)))),
+                         seed=2000 + i))
+    return dict(name="batch360_uneven16", phantoms=phantoms, jobs=jobs,
+                geometry=base["geometry"], spectrum=base["spectrum"])
+

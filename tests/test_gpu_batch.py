@@ -136,3 +136,54 @@ def test_batch_errors(torch_gpu):
     with pytest.raises(mcx.MCXError):     # unknown phantom
         mcx.mc_project_batch(g.ctx, [dict(phantom=3, angle_rad=0.0, n_photons=10, seed=0,
                                           primary_offset=0, scatter_offset=2000)], big, 5000)
+
+
+def test_batch_full_workload(torch_gpu):
+    """The benchmark's batch (360 angles x 1e7 photons of the 256^3 object plus
+    16 objects of 64^3 .. 384^3) in one graph-replayed launch: two replays are
+    equal, sampled jobs equal their single projections bitwise, and the job on
+    the smallest object equals the oracle."""
+    torch = torch_gpu
+    w = inputs.batch_workload()
+    geo = w["geometry"]
+    g = mcx.Projector(0)
+    g.set_spectrum(*w["spectrum"])
+    g.set_geometry(**geo)
+    g.load_phantom(*w["phantoms"][0])
+    handles = [0] + [mcx.mc_phantom_add(g.ctx, a, b, h) for a, b, h in w["phantoms"][1:]]
+    np_, ns_ = geo["nu"] * geo["nv"], geo["snu"] * geo["snv"]
+    jobs = [dict(j, phantom=handles[j["phantom"]], primary_offset=i * (np_ + ns_),
+                 scatter_offset=i * (np_ + ns_) + np_) for i, j in enumerate(w["jobs"])]
+    out = torch.empty(len(jobs) * (np_ + ns_), dtype=torch.int64, device="cuda")
+    say("batch full workload", len(jobs), "jobs")
+    mcx.mc_project_batch(g.ctx, jobs, out, out.numel(), flags=mcx.MC_BATCH_GRAPH)
+    first = out.clone()
+    mcx.mc_project_batch(g.ctx, jobs, out, out.numel(), flags=mcx.MC_BATCH_GRAPH)
+    torch.cuda.synchronize()
+    assert torch.equal(first, out)
+    p = torch.empty((geo["nv"], geo["nu"]), dtype=torch.int64, device="cuda")
+    s = torch.empty((geo["snv"], geo["snu"]), dtype=torch.int64, device="cuda")
+    smallest = 360                                   # the 64^3 object
+    for i in (0, 359, smallest, len(jobs) - 1):
+        j = w["jobs"][i]
+        ids, rho, h = w["phantoms"][j["phantom"]]
+        single = mcx.Projector(0)
+        single.set_spectrum(*w["spectrum"])
+        single.set_geometry(**geo)
+        single.load_phantom(ids, rho, h)
+        mcx.mc_project_async(single.ctx, j["angle_rad"], j["n_photons"], j["seed"], p, s)
+        torch.cuda.synchronize()
+        say("job", i, "object", ids.shape, "photons", j["n_photons"])
+        assert torch.equal(p.view(-1), out[i * (np_ + ns_):i * (np_ + ns_) + np_]), i
+        assert torch.equal(s.view(-1), out[i * (np_ + ns_) + np_:(i + 1) * (np_ + ns_)]), i
+        single.close()
+    j = w["jobs"][smallest]
+    ids, rho, h = w["phantoms"][j["phantom"]]
+    o = oracle.Oracle()
+    o.load_phantom(ids, rho, h)
+    o.set_geometry(**geo)
+    o.set_spectrum(*w["spectrum"])
+    rp, rs = o.project(j["angle_rad"], j["n_photons"], j["seed"], threads=16)
+    b = smallest * (np_ + ns_)
+    assert np.array_equal(out[b:b + np_].cpu().numpy().reshape(rp.shape), rp)
+    assert np.array_equal(out[b + np_:b + np_ + ns_].cpu().numpy().reshape(rs.shape), rs)
