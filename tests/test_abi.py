@@ -61,6 +61,15 @@ def test_host_context_validation(host_ctx):
     with pytest.raises(mcx.MCXError) as e:
         mcx.mc_load_phantom(ctx, ids, rho, 1.0)
     assert e.value.code == mcx.MC_E_STATE
+    # an x-y slab of bricks beyond the kernel's 24-bit strides is refused as too large,
+    # the largest accepted one reaches validation's end (no device)
+    big_ids, big_rho = np.zeros((1, 2048, 2049), np.uint8), np.ones((1, 2048, 2049), np.float32)
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_load_phantom(ctx, big_ids, big_rho, 0.01)
+    assert e.value.code == mcx.MC_E_INVALID_ARG and "too large" in str(e.value)
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_load_phantom(ctx, big_ids[:, :, :2048], big_rho[:, :, :2048], 0.01)
+    assert e.value.code == mcx.MC_E_STATE
     with pytest.raises(mcx.MCXError):
         mcx.mc_set_geometry(ctx, 500, 400, 10, 10, 1, 1, 0.5)        # sdd < sod
     with pytest.raises(mcx.MCXError):
