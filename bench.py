@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--workload", default="ellipsoids256_poly")
     ap.add_argument("--photons", type=int, default=0, help="override photons per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
@@ -239,6 +240,33 @@ def main():
     log(f"{n * args.steps / wall:.4g} histories/s, {launch_s * 1e3:.2f} ms per step (events), "
         f"steps/history {st['steps'] / max(st['histories'], 1):.1f}")
 
+    # march ceiling: the probe's gathers alone, same object and launch shape
+    probe = None
+    if not args.no_probe:
+        log("march probe")
+        best = None
+        n_rays = 30_000_000
+        d = torch.zeros(2, dtype=torch.int64, device=dev)
+        for refill in (8, 16, 40):
+            mcx.mc_march_probe_async(g.ctx, w["angle"], n_rays, w["seed"], refill, d, stream)
+            torch.cuda.synchronize()
+            d.zero_()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(3):
+                mcx.mc_march_probe_async(g.ctx, w["angle"], n_rays, w["seed"], refill, d, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            rate = int(d[1].item()) / (a.elapsed_time(b) * 1e-3)
+            if best is None or rate > best[0]:
+                best = (rate, refill)
+        t_rate = st["steps"] / launch_s
+        probe = {"steps_per_s": best[0], "refill_batch": best[1], "rays": n_rays,
+                 "gather_GBs": best[0] * gather_bytes / 1e9,
+                 "transport_steps_per_s": t_rate, "frac": t_rate / best[0]}
+        log(f"march ceiling {best[0]:.4g} steps/s (refill {best[1]}), transport "
+            f"{t_rate:.4g} steps/s = {t_rate / best[0]:.1%}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -285,6 +313,7 @@ def main():
             "gather": {"algorithmic_bytes_per_launch": alg_bytes,
                        "bytes_per_step": gather_bytes, "achieved_GBs": gather_gbs,
                        "hbm_peak_GBs": HBM_PEAK_GBS, "frac": gather_gbs / HBM_PEAK_GBS},
+            "march_ceiling": probe,
         },
         "cpu_baseline": cpu,
     }

@@ -186,6 +186,21 @@ typedef struct mc_job {
 mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t *d_out,
                            uint64_t out_elems, uint32_t flags, void *stream);
 
+/* March probe (a measuring instrument, not part of the method): n_rays
+ * straight rays with the birth directions of photons 0 .. n_rays-1 of `seed`
+ * are marched through the loaded object with the transport's fixed-step rule
+ * (section II-C-2 as the transport reads it: the same step centres, clamps,
+ * voxel layout and prefetch groups) and nothing else -- no optical depth,
+ * interactions or tallies.  Lanes are refilled once refill_batch (1 .. 64)
+ * of a wave's lanes are idle.  Adds the sum of the gathered voxel codes
+ * (palette index or material id, plus the low bit of the density in the
+ * generic layout) to d_sum[0] and the number of steps taken to d_sum[1]
+ * (device uint64[2], not cleared).  Stream-ordered, same launch shape as
+ * the transport.  Its step rate is the ceiling of the transport's march on
+ * the same object. */
+mc_status mc_march_probe_async(mc_ctx *ctx, float angle_rad, uint64_t n_rays, uint64_t seed,
+                               int refill_batch, uint64_t *d_sum, void *stream);
+
 /* Per-history record of photons first .. first+m-1 (blocking, host outputs,
  * any of them may be NULL): scatterings, march steps, end code (MC_END_*),
  * and the type of the first interaction (0 none, 1 photo, 2 Rayleigh,

@@ -21,6 +21,8 @@
 #include "tables.hpp"
 
 namespace mcx {
+hipError_t launch_march_probe(const KParams &p, int layout, int grid, int block,
+                              unsigned long long *sum, hipStream_t stream);
 hipError_t launch_transport(const KParams &p, int layout, int grid, int block, bool stats,
                             bool debug, hipStream_t stream);
 hipError_t launch_sample(const KParams &p, int process, int material, float e_kev, uint64_t n,
@@ -700,6 +702,29 @@ mc_status mc_project_async(mc_ctx *c, float beta, uint64_t n, uint64_t seed, int
     p.prim = (unsigned long long *)d_prim;
     p.scat = (unsigned long long *)d_scat;
     return run(c, p, s, false);
+}
+
+mc_status mc_march_probe_async(mc_ctx *c, float beta, uint64_t n_rays, uint64_t seed,
+                               int refill_batch, uint64_t *d_sum, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_sum) return fail(c, MC_E_INVALID_ARG, "null sum");
+    if (refill_batch < 1 || refill_batch > 64)
+        return fail(c, MC_E_INVALID_ARG, "refill_batch must be 1 .. 64");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    KParams p;
+    rc = prepare(c, beta, 0, n_rays, seed, p);
+    if (rc) return rc;
+    if (n_rays == 0) return MC_OK;
+    p.event_batch = refill_batch;
+    p.stats = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(c, hipMemsetAsync(p.counter, 0, sizeof(unsigned long long), s));
+    int grid, block;
+    launch_shape(c, p, p.G.layout, false, grid, block);
+    hipError_t e = launch_march_probe(p, p.G.layout, grid, block, (unsigned long long *)d_sum, s);
+    if (e != hipSuccess) return hip_fail(c, e, "march probe launch");
+    return MC_OK;
 }
 
 mc_status mc_project(mc_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *prim,

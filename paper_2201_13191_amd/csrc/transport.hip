@@ -208,6 +208,18 @@ __device__ __forceinline__ bool panel_hit(const KParams &p, const ProjFrame &F, 
     return true;
 }
 
+// birth direction inside the cone that circumscribes the panel: cos theta
+// uniform on [cos theta_max, 1], azimuth uniform (two draws)
+__device__ __forceinline__ void cone_direction(const ProjFrame &F, PhotonStream &rng, float d[3]) {
+    const float ct = 1.0f - rng.u() * F.omc;
+    const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    double sphi, cphi;
+    sincos(6.283185307179586 * (double)rng.u(), &sphi, &cphi);
+    const float cp = (float)cphi, sp = (float)sphi;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = (ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
+}
+
 // ------------------------------------------------------------------ kernels
 enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim, kStScat,
              kStCut, kStCap, kStCount };
@@ -314,16 +326,9 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         rng.reset(pid, k0, k1);
         e = p.e_bin[pick_bin(p, rng.raw())];
         const ProjFrame &F = frame();
-        const float ct = 1.0f - rng.u() * F.omc;
-        const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-        double sphi, cphi;
-        sincos(6.283185307179586 * (double)rng.u(), &sphi, &cphi);
-        const float cp = (float)cphi, sp = (float)sphi;
+        cone_direction(F, rng, d);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            d[a] = (ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
-            o[a] = F.S[a];
-        }
+        for (int a = 0; a < 3; ++a) o[a] = F.S[a];
         refresh_mu(e);
         n_int = 0;
         alive = true;
@@ -558,6 +563,93 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     }
 }
 
+// March probe: the voxel gathers of the march and nothing else.  Each lane
+// takes rays (the birth directions of photon ids from the launch counter)
+// and marches each straight through the object with the transport's step
+// centres, clamps, layout and prefetch groups, adding up the codes it
+// gathers (sum[0]) and the steps it takes (sum[1]); no optical depth,
+// interactions, energies or tallies.  Dead lanes are refilled once
+// `event_batch` of them wait.  Its step rate is the
+// ceiling of the transport's march on the same object and launch shape.
+template <int MODE>
+__global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
+                                                          unsigned long long *sum) {
+    const int lane = (int)__lane_id();
+    const VoxelGrid &gl = p.G;
+    bool alive = false, exhausted = false;
+    float q[3] = {0.0f, 0.0f, 0.0f}, G[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t k = 0, nsteps = 0;
+    unsigned long long acc = 0, taken = 0;
+    for (;;) {
+        if (!exhausted && __popcll(__ballot(!alive)) >= (unsigned)p.event_batch) {
+            const unsigned long long dead = __ballot(!alive);
+            const unsigned nd = (unsigned)__popcll(dead);
+            const int leader = __ffsll(dead) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(p.counter, (unsigned long long)nd);
+            base = __shfl(base, leader);
+            const unsigned long long got =
+                base < p.n ? (p.n - base < nd ? p.n - base : nd) : 0ull;
+            if (got < nd) exhausted = true;
+            if (!alive) {
+                const unsigned long long rank =
+                    (unsigned long long)__popcll(dead & ((1ull << lane) - 1ull));
+                if (rank < got) {
+                    PhotonStream rng;
+                    rng.reset(p.first + base + rank, p.key0, p.key1);
+                    (void)rng.raw();                       // the energy draw
+                    float o[3], d[3], tin, tout;
+                    cone_direction(p.F, rng, d);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) o[a] = p.F.S[a];
+                    if (box_entry(gl, o, d, tin, tout)) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const float pin = o[a] + d[a] * tin;
+                            G[a] = (d[a] * gl.inv_h) * p.step;
+                            q[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                        }
+                        nsteps = step_count(tout - tin, p.step);
+                        k = 0;
+                        alive = nsteps > 0u;
+                    }
+                }
+            }
+        }
+        if (!__any(alive)) {
+            if (exhausted) break;
+            continue;
+        }
+        if (alive) {
+            uint32_t code[kPrefetch];
+            float vr[kPrefetch];
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const uint32_t off = brick_offset(gl, voxel_index(q[0], gl.cmax[0]),
+                                                  voxel_index(q[1], gl.cmax[1]),
+                                                  voxel_index(q[2], gl.cmax[2]));
+                code[u] = gl.vox[off];
+                if (MODE == kGeneric) vr[u] = gl.vrho[off];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+            }
+            const uint32_t rem = nsteps - k;
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                uint32_t c = code[u];
+                if (MODE == kGeneric) c += __float_as_uint(vr[u]) & 1u;
+                acc += (uint32_t)u < rem ? c : 0u;
+            }
+            taken += rem < (uint32_t)kPrefetch ? rem : (uint32_t)kPrefetch;
+            k += kPrefetch;
+            if (k >= nsteps) alive = false;
+        }
+    }
+    const unsigned long long t = wave_sum(acc), ns = wave_sum(taken);
+    if (lane == 0 && t) atomicAdd(sum, t);
+    if (lane == 0 && ns) atomicAdd(sum + 1, ns);
+}
+
 __global__ void sample_kernel(const KParams p, int process, int material, float e_kev,
                               uint64_t n, float *cos_out, float *e_out) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -623,6 +715,20 @@ hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int bl
     else
         hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, false, false>), dim3(grid),
                            dim3(block), lds, stream, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_march_probe(const KParams &p, int layout, int grid, int block,
+                              unsigned long long *sum, hipStream_t stream) {
+    if (layout == kPaletteLane)
+        hipLaunchKernelGGL(march_probe_kernel<kPaletteLane>, dim3(grid), dim3(block), 0, stream,
+                           p, sum);
+    else if (layout == kPaletteShared)
+        hipLaunchKernelGGL(march_probe_kernel<kPaletteShared>, dim3(grid), dim3(block), 0,
+                           stream, p, sum);
+    else
+        hipLaunchKernelGGL(march_probe_kernel<kGeneric>, dim3(grid), dim3(block), 0, stream, p,
+                           sum);
     return hipGetLastError();
 }
 

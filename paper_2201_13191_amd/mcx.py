@@ -31,7 +31,8 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_upsample_cubic_async", "mc_savgol_weights", "mc_nn_conv3x3_async",
            "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
-           "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async"]
+           "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
+           "mc_march_probe_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -105,6 +106,7 @@ def load():
         "mc_project": ([P, F, U64, U64, P, P], I),
         "mc_project_async": ([P, F, U64, U64, P, P, P], I),
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
+        "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
         "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
         "mc_set_stats": ([P, I], I),
@@ -247,6 +249,11 @@ def mc_project(ctx, angle, n_photons, seed, primary, scatter):
 def mc_project_async(ctx, angle, n_photons, seed, d_primary, d_scatter, stream=None):
     _check(ctx, load().mc_project_async(ctx, angle, n_photons, seed, _dev(d_primary),
                                         _dev(d_scatter), _stream(stream)))
+
+
+def mc_march_probe_async(ctx, angle, n_rays, seed, refill_batch, d_sum, stream=None):
+    _check(ctx, load().mc_march_probe_async(ctx, angle, n_rays, seed, refill_batch, _dev(d_sum),
+                                            _stream(stream)))
 
 
 def mc_project_range_async(ctx, angle, first, n, seed, d_primary, d_scatter, stream=None):
