@@ -247,7 +247,8 @@ def main():
         best = None
         n_rays = 30_000_000
         d = torch.zeros(2, dtype=torch.int64, device=dev)
-        for refill in (8, 16, 40):
+        for bpc, refill in ((0, 8), (0, 16), (0, 40), (8, 16), (8, 40)):
+            g.set_launch(0, bpc, 0)
             mcx.mc_march_probe_async(g.ctx, w["angle"], n_rays, w["seed"], refill, d, stream)
             torch.cuda.synchronize()
             d.zero_()
@@ -259,9 +260,11 @@ def main():
             torch.cuda.synchronize()
             rate = int(d[1].item()) / (a.elapsed_time(b) * 1e-3)
             if best is None or rate > best[0]:
-                best = (rate, refill)
+                best = (rate, refill, bpc)
+        g.set_launch(0, 0, 0)
         t_rate = st["steps"] / launch_s
-        probe = {"steps_per_s": best[0], "refill_batch": best[1], "rays": n_rays,
+        probe = {"steps_per_s": best[0], "refill_batch": best[1],
+                 "blocks_per_cu": best[2] or "occupancy", "rays": n_rays,
                  "gather_GBs": best[0] * gather_bytes / 1e9,
                  "transport_steps_per_s": t_rate, "frac": t_rate / best[0]}
         log(f"march ceiling {best[0]:.4g} steps/s (refill {best[1]}), transport "

@@ -195,9 +195,10 @@ mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t 
  * of a wave's lanes are idle.  Adds the sum of the gathered voxel codes
  * (palette index or material id, plus the low bit of the density in the
  * generic layout) to d_sum[0] and the number of steps taken to d_sum[1]
- * (device uint64[2], not cleared).  Stream-ordered, same launch shape as
- * the transport.  Its step rate is the ceiling of the transport's march on
- * the same object. */
+ * (device uint64[2], not cleared).  Stream-ordered; the block size and
+ * blocks per compute unit of mc_set_launch apply, and automatic blocks per
+ * CU means the probe's own occupancy.  Its step rate is the ceiling of the
+ * transport's march on the same object. */
 mc_status mc_march_probe_async(mc_ctx *ctx, float angle_rad, uint64_t n_rays, uint64_t seed,
                                int refill_batch, uint64_t *d_sum, void *stream);
 

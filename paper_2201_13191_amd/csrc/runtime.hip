@@ -23,6 +23,7 @@
 namespace mcx {
 hipError_t launch_march_probe(const KParams &p, int layout, int grid, int block,
                               unsigned long long *sum, hipStream_t stream);
+int march_probe_blocks_per_cu(int layout, int block);
 hipError_t launch_transport(const KParams &p, int layout, int grid, int block, bool stats,
                             bool debug, hipStream_t stream);
 hipError_t launch_sample(const KParams &p, int process, int material, float e_kev, uint64_t n,
@@ -64,7 +65,7 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 40;
+constexpr int kDefaultEventBatch = 48;
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or
@@ -720,8 +721,12 @@ mc_status mc_march_probe_async(mc_ctx *c, float beta, uint64_t n_rays, uint64_t 
     p.stats = nullptr;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(c, hipMemsetAsync(p.counter, 0, sizeof(unsigned long long), s));
-    int grid, block;
-    launch_shape(c, p, p.G.layout, false, grid, block);
+    // the probe's own occupancy (it uses no LDS) unless the caller fixed a shape
+    const int block = c->block > 0 ? c->block : 256;
+    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
+                                         : march_probe_blocks_per_cu(p.G.layout, block);
+    const uint64_t need = (n_rays + block - 1) / block;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, need));
     hipError_t e = launch_march_probe(p, p.G.layout, grid, block, (unsigned long long *)d_sum, s);
     if (e != hipSuccess) return hip_fail(c, e, "march probe launch");
     return MC_OK;

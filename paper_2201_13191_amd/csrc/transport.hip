@@ -225,7 +225,7 @@ enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim
              kStCut, kStCap, kStCount };
 
 #ifndef MCX_PREFETCH
-#define MCX_PREFETCH 4
+#define MCX_PREFETCH 8
 #endif
 constexpr int kPrefetch = MCX_PREFETCH;   // march steps whose voxel loads are issued together
 constexpr int kLdsHeader = 256 + 64;   // floats: palette densities, then 256 palette ids
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
 // gathers (sum[0]) and the steps it takes (sum[1]); no optical depth,
 // interactions, energies or tallies.  Dead lanes are refilled once
 // `event_batch` of them wait.  Its step rate is the
-// ceiling of the transport's march on the same object and launch shape.
+// ceiling of the transport's march on the same object.
 template <int MODE>
 __global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
                                                           unsigned long long *sum) {
@@ -770,6 +770,20 @@ static int occupancy(int block, size_t lds, bool stats) {
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, transport_kernel<MODE, BATCH, false, false>, block, lds);
     return nb;
+}
+
+int march_probe_blocks_per_cu(int layout, int block) {
+    int nb = 0;
+    if (layout == kPaletteLane)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march_probe_kernel<kPaletteLane>,
+                                                           block, 0);
+    else if (layout == kPaletteShared)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, march_probe_kernel<kPaletteShared>, block, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march_probe_kernel<kGeneric>,
+                                                           block, 0);
+    return nb > 0 ? nb : 1;
 }
 
 int transport_blocks_per_cu(const KParams &p, int layout, int block, bool stats) {
