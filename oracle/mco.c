@@ -587,34 +587,43 @@ typedef struct {
     uint8_t end, first;
 } hist_t;
 
+/* Optical-depth increments are kept on the grid of 2^-32 (and below 2^21),
+ * where fp64 sums are exact: the optical depth after any run of steps does
+ * not depend on how the additions are grouped. */
+static double on_grid(double x) { return ldexp(rint(ldexp(x, 32)), -32); }
+
 /* Fixed-step march from entry t_in to exit t_out (section II-C-2 fixes only
  * that the step size is a free parameter; this discretisation is the one
  * both implementations follow).  L = t_out - t_in.  Step k starts at
- * a_k = k*step (one fp32 product) and is taken while a_k < L; it has length
- * step, except the last one (the first k with (k+1)*step >= L), whose length
- * is L - a_k.  Its voxel contains the step's nominal centre (k + 1/2)*step,
- * kept in voxel coordinates and advanced by repeated addition:
- * c_0 = (p_in - lo)/h + G/2 and c_{k+1} = c_k + G with G = (d/h)*step,
- * truncated and clamped to the object.  The photon interacts in the first
- * step where the accumulated optical depth reaches tau_star, at the linearly
- * interpolated point a_k + (tau_star - tau)/mu.  Returns 1 with the
- * interaction point and voxel. */
+ * a_k = k*step (one fp32 product) and is taken while a_k < L; it is a full
+ * step except the last one (the first k with (k+1)*step >= L), of length
+ * l = L - a_k.  Its voxel contains the step's nominal centre (k + 1/2)*step
+ * in voxel coordinates: with G = (d/h)*step and c_0 = (p_in - lo)/h + G/2,
+ * c_k = c_0 + k*G for k a multiple of 4 and c_k = c_{k-1} + G otherwise
+ * (fp32, each operation rounded), truncated and clamped to the object.
+ * Optical depth: a full step adds on_grid(mu*step) (fp64 product of the fp32
+ * values), the last one on_grid(that * min(1, l/step)); the sum is fp64 and
+ * exact.  The photon interacts in the first step where it reaches tau_star,
+ * at a_k + (tau_star - tau)/inc * length (fp64, rounded to fp32).  Returns 1
+ * with the interaction point and voxel. */
 static int march(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
                  float tin, float tout, const float *mm, float tau_star, float pint[3],
                  size_t *vox, uint32_t *steps) {
     const float dl = c->g.step_mm;
-    float pin[3], q[3], G[3];
+    float pin[3], c0[3], G[3], q[3];
     for (int a = 0; a < 3; ++a) pin[a] = p[a] + d[a] * tin;
     float L = tout - tin;
     for (int a = 0; a < 3; ++a) {
         G[a] = (d[a] * P->inv_h) * dl;
-        q[a] = (pin[a] - P->lo[a]) * P->inv_h + 0.5f * G[a];
+        c0[a] = (pin[a] - P->lo[a]) * P->inv_h + 0.5f * G[a];
     }
-    float tau = 0.0f;
+    const double ts = (double)tau_star;
+    double tau = 0.0;
     for (uint32_t k = 0;; ++k) {
         float a0 = (float)k * dl;
         if (!(a0 < L)) return 0;
-        float dk = ((float)(k + 1u) * dl < L) ? dl : L - a0;
+        for (int a = 0; a < 3; ++a)
+            q[a] = (k & 3u) == 0u ? c0[a] + (float)k * G[a] : q[a] + G[a];
         int ix = (int)q[0];
         int iy = (int)q[1];
         int iz = (int)q[2];
@@ -623,17 +632,22 @@ static int march(const mco_ctx *c, const proj_t *P, const float p[3], const floa
         iz = iz < 0 ? 0 : (iz > c->nz - 1 ? c->nz - 1 : iz);
         size_t v = ((size_t)iz * c->ny + iy) * c->nx + ix;
         float mu = c->rho[v] * mm[c->ids[v]];
-        float x = mu * dk;
-        float tnext = tau + x;
+        double inc = on_grid((double)mu * (double)dl);
+        float len = dl;
+        if (!((float)(k + 1u) * dl < L)) {            /* the last, clipped step */
+            len = L - a0;
+            double r = (double)len / (double)dl;
+            if (r > 1.0) r = 1.0;
+            inc = on_grid(inc * r);
+        }
         (*steps)++;
-        if (tnext >= tau_star) {
-            float sint = a0 + (tau_star - tau) / mu;
+        if (tau + inc >= ts) {
+            float sint = a0 + (float)((ts - tau) / inc * (double)len);
             for (int a = 0; a < 3; ++a) pint[a] = pin[a] + d[a] * sint;
             *vox = v;
             return 1;
         }
-        tau = tnext;
-        for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+        tau = tau + inc;
     }
 }
 

@@ -28,8 +28,7 @@ CASES = [
      "test_oracle_samplers.py::test_rayleigh_angles_chi2"),
     ("rayleigh_thomson", "0.5 * (1.0 + cd * cd)", "0.5 * (1.0 + cd)",
      "test_oracle_samplers.py::test_rayleigh_angles_chi2"),
-    ("last_step_unclipped", "float dk = ((float)(k + 1u) * dl < L) ? dl : L - a0;",
-     "float dk = dl;",
+    ("last_step_unclipped", "inc = on_grid(inc * r);", "inc = on_grid(inc);",
      "test_oracle_transport.py::test_beer_lambert_slab"),
     ("midpoint_dropped", "* P->inv_h + 0.5f * G[a];", "* P->inv_h;",
      "test_oracle_transport.py::test_tiny_phantom_primary_brute_force"),
