@@ -100,11 +100,13 @@ typedef struct mc_geometry {
 /* Counters accumulated by projections run while statistics are enabled. */
 typedef struct mc_stats {
     uint64_t histories;
-    uint64_t steps;        /* voxel lookups of the march                 */
+    uint64_t steps;        /* fixed steps of the march                   */
     uint64_t flights;
     uint64_t photo, rayleigh, compton;
     uint64_t primary_hits, scatter_hits;
     uint64_t cutoff_kills, cap_hits;
+    uint64_t skipped_steps;  /* steps (included in `steps`) taken as runs through
+                                uniform regions without a voxel lookup each     */
 } mc_stats;
 
 /* Create a context on HIP device `device`; allocates only small buffers.
@@ -201,6 +203,17 @@ mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t 
  * transport's march on the same object. */
 mc_status mc_march_probe_async(mc_ctx *ctx, float angle_rad, uint64_t n_rays, uint64_t seed,
                                int refill_batch, uint64_t *d_sum, void *stream);
+
+/* Uniform-cell map of a voxel object, as the march uses it to take runs of
+ * identical voxels at once (host only, no context): codes[nz][ny][nx] are
+ * per-voxel codes (the palette index of each (material, density) pair);
+ * cells[ceil(nz/8)][ceil(ny/8)][ceil(nx/8)] receives, per cube of 8x8x8
+ * voxels (clipped to the object), code | r << 8 where r >= 1 means that every
+ * cell within Chebyshev distance r - 1 (indices clamped to the grid) holds
+ * only that code (r capped at 255), and 0 for a cell holding several codes.
+ * A run of fixed steps whose centres stay inside such a cube has one
+ * optical-depth increment per step (section II-C-2's march is unchanged). */
+mc_status mc_cell_map(const uint8_t *codes, int nx, int ny, int nz, uint16_t *cells);
 
 /* Per-history record of photons first .. first+m-1 (blocking, host outputs,
  * any of them may be NULL): scatterings, march steps, end code (MC_END_*),

@@ -23,7 +23,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math"
 
 SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
            ("runtime.hip", "hip"),
-           ("tables.cpp", "cxx"), ("autotune.cpp", "hiphost")]
+           ("tables.cpp", "cxx"), ("cells.cpp", "cxx"), ("autotune.cpp", "hiphost")]
 
 
 def _compile(src, kind):

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mcx.h"
+#include "cells.hpp"
 #include "kernel_params.hpp"
 #include "nn_params.hpp"
 #include "tables.hpp"
@@ -80,15 +81,19 @@ struct Phantom {
     uint8_t *d_vox = nullptr;
     float *d_vrho = nullptr;
     unsigned char *d_pal = nullptr;     // 256 densities (f32) then 256 ids (u8)
+    uint16_t *d_cells = nullptr;        // uniform-cell map (palette layouts)
+    int ncx = 0, ncy = 0, ncz = 0;
     bool loaded = false;
 
     void release() {
         if (d_vox) (void)hipFree(d_vox);
         if (d_vrho) (void)hipFree(d_vrho);
         if (d_pal) (void)hipFree(d_pal);
+        if (d_cells) (void)hipFree(d_cells);
         d_vox = nullptr;
         d_vrho = nullptr;
         d_pal = nullptr;
+        d_cells = nullptr;
         loaded = false;
     }
 };
@@ -291,6 +296,11 @@ VoxelGrid grid_of(const mc_ctx *c, const Phantom &ph) {
     G.cmax[1] = (float)(ph.ny - 1);
     G.cmax[2] = (float)(ph.nz - 1);
     G.inv_h = 1.0f / ph.h;
+    // runs of identical voxels are skipped where the lane keeps per-palette
+    // optical-depth increments
+    G.cells = G.layout == kPaletteLane ? ph.d_cells : nullptr;
+    G.ncx = ph.ncx;
+    G.ncy = ph.ncy;
     const int nd[3] = {ph.nx, ph.ny, ph.nz};
     for (int a = 0; a < 3; ++a) {
         G.hi[a] = 0.5f * ((float)nd[a] * ph.h);
@@ -523,10 +533,15 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                                          "distinct (material, density) pairs");
     mc_status rc = use_device(c);
     if (rc) return rc;
-    // bricked host images
+    // bricked host images, and the code of each uniform 8^3 cell (-1: mixed)
     std::vector<uint8_t> vox(padded, 0);
     std::vector<float> vr;
     if (!palette_ok) vr.assign(padded, 0.0f);
+    const int ncx = (nx + (1 << kCellLog) - 1) >> kCellLog;
+    const int ncy = (ny + (1 << kCellLog) - 1) >> kCellLog;
+    const int ncz = (nz + (1 << kCellLog) - 1) >> kCellLog;
+    std::vector<int16_t> cell_code;
+    if (palette_ok) cell_code.assign((size_t)ncx * ncy * ncz, -2);   // -2: no voxel seen yet
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
             const size_t row = ((size_t)z * ny + y) * nx;
@@ -551,8 +566,16 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                     last_code = (uint8_t)slot_pal[hsh];
                 }
                 vox[off] = last_code;
+                int16_t &cc = cell_code[((size_t)(z >> kCellLog) * ncy + (y >> kCellLog)) * ncx +
+                                        (x >> kCellLog)];
+                if (cc == -2)
+                    cc = last_code;
+                else if (cc != last_code)
+                    cc = -1;
             }
         }
+    std::vector<uint16_t> cells;
+    if (palette_ok) cell_radii(ncx, ncy, ncz, cell_code, cells);
     HIP_TRY(c, hipDeviceSynchronize());
     out.release();
     HIP_TRY(c, hipMalloc(&out.d_vox, padded));
@@ -566,7 +589,11 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
         std::memcpy(pal + 256 * 4, pal_id, (size_t)n_pal);
         HIP_TRY(c, hipMalloc(&out.d_pal, sizeof pal));
         HIP_TRY(c, hipMemcpy(out.d_pal, pal, sizeof pal, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMalloc(&out.d_cells, cells.size() * sizeof(uint16_t)));
+        HIP_TRY(c, hipMemcpy(out.d_cells, cells.data(), cells.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice));
     }
+    out.ncx = ncx; out.ncy = ncy; out.ncz = ncz;
     out.nx = nx; out.ny = ny; out.nz = nz; out.h = h;
     out.nbx = nbx; out.nby = nby; out.nbz = nbz;
     out.max_id = max_id;
@@ -580,6 +607,30 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
 }  // namespace
 
 extern "C" {
+
+mc_status mc_cell_map(const uint8_t *codes, int nx, int ny, int nz, uint16_t *cells) {
+    if (!codes || !cells || nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+        return MC_E_INVALID_ARG;
+    const int ncx = (nx + (1 << kCellLog) - 1) >> kCellLog;
+    const int ncy = (ny + (1 << kCellLog) - 1) >> kCellLog;
+    const int ncz = (nz + (1 << kCellLog) - 1) >> kCellLog;
+    std::vector<int16_t> code((size_t)ncx * ncy * ncz, -2);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const uint8_t v = codes[((size_t)z * ny + y) * nx + x];
+                int16_t &cc = code[((size_t)(z >> kCellLog) * ncy + (y >> kCellLog)) * ncx +
+                                   (x >> kCellLog)];
+                if (cc == -2)
+                    cc = v;
+                else if (cc != v)
+                    cc = -1;
+            }
+    std::vector<uint16_t> out;
+    cell_radii(ncx, ncy, ncz, code, out);
+    std::memcpy(cells, out.data(), out.size() * sizeof(uint16_t));
+    return MC_OK;
+}
 
 mc_status mc_load_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx, int ny,
                           int nz, float h) {
@@ -991,6 +1042,7 @@ mc_status mc_get_stats(mc_ctx *c, mc_stats *out) {
     out->photo = h[3]; out->rayleigh = h[4]; out->compton = h[5];
     out->primary_hits = h[6]; out->scatter_hits = h[7];
     out->cutoff_kills = h[8]; out->cap_hits = h[9];
+    out->skipped_steps = h[10];
     return MC_OK;
 }
 

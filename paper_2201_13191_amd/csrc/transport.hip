@@ -222,7 +222,16 @@ __device__ __forceinline__ void cone_direction(const ProjFrame &F, PhotonStream 
 
 // ------------------------------------------------------------------ kernels
 enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim, kStScat,
-             kStCut, kStCap, kStCount };
+             kStCut, kStCap, kStSkipped, kStCount };
+
+// optical-depth increments on the grid of 2^-32: fp64 sums of them are exact,
+// so a run of equal increments can be added at once
+__device__ __forceinline__ double on_grid(double x) {
+    return __builtin_rint(x * 4294967296.0) * 2.3283064365386963e-10;
+}
+
+constexpr float kSkipMargin = 1.0f / 64.0f;   // voxels kept from a uniform region's faces
+constexpr uint32_t kMinSkip = 8;             // shortest run taken at once
 
 #ifndef MCX_PREFETCH
 #define MCX_PREFETCH 8
@@ -271,15 +280,17 @@ __device__ __forceinline__ uint32_t voxel_index(float c, float cmax) {
 template <int MODE, bool BATCH, bool STATS, bool DEBUG>
 __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     // LDS: palette densities [256] | palette ids [256 bytes] (single object only) |
-    // lane-private columns: mu per material [n_mat][bs], then mu per palette
-    // entry [n_pal][bs] for per-lane palette tables
+    // lane-private columns: mu per material [n_mat][bs] (fp32), then the
+    // optical-depth increment of a full step per palette entry [n_pal][bs]
+    // (fp64) for per-lane palette tables
     extern __shared__ float lds[];
     float *s_pal_rho = lds;
     uint8_t *s_pal_id = (uint8_t *)(lds + 256);
     const int bs = blockDim.x;
     float *mm = lds + kLdsHeader + threadIdx.x;
-    float *mu_pal = mm + p.n_mat * bs;
-    const uint32_t bs4 = (uint32_t)bs * 4u;   // byte stride between a lane's LDS entries
+    double *inc_pal = (double *)(lds + kLdsHeader + p.n_mat * bs) + threadIdx.x;
+    const uint32_t bs8 = (uint32_t)bs * 8u;   // byte stride between a lane's fp64 entries
+    const double step32 = (double)p.step * 4294967296.0;
     const int lane = (int)__lane_id();
     if (!BATCH && MODE != kGeneric) {
         for (int i = threadIdx.x; i < p.G.n_pal; i += bs) {
@@ -300,24 +311,30 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     uint64_t pid = 0;
     float e = 0.0f;
     float o[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
-    float q[3], G[3];
-    float tin = 0.0f, last = 0.0f, tau = 0.0f, tau_star = 0.0f;
+    float c0[3], q[3], G[3], ig[3];
+    float tin = 0.0f, last = 0.0f;
+    double tau = 0.0, ts = 0.0;
     uint32_t k = 0, nsteps = 0;
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
     uint8_t h_first = 0;
 
-    // attenuation at the photon's energy: per material, and per palette entry
+    // attenuation at the photon's energy: per material, and the full-step
+    // optical-depth increment per palette entry
     auto refresh_mu = [&](float energy) {
         material_mu(p, energy, mm, bs);
         if (BATCH) {
             if (gl.layout == kPaletteLane)
-                for (int c = 0; c < gl.n_pal; ++c)
-                    mu_pal[c * bs] = gl.pal_rho[c] * mm[gl.pal_id[c] * bs];
+                for (int c = 0; c < gl.n_pal; ++c) {
+                    const float mu = gl.pal_rho[c] * mm[gl.pal_id[c] * bs];
+                    inc_pal[c * bs] = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
+                }
         } else if (MODE == kPaletteLane) {
-            for (int c = 0; c < p.G.n_pal; ++c)
-                mu_pal[c * bs] = s_pal_rho[c] * mm[s_pal_id[c] * bs];
+            for (int c = 0; c < p.G.n_pal; ++c) {
+                const float mu = s_pal_rho[c] * mm[s_pal_id[c] * bs];
+                inc_pal[c * bs] = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
+            }
         }
     };
     // a new photon: energy bin, direction in the cone, position at the source
@@ -459,19 +476,21 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         if (alive && !flying && event == 0) {
             float tout;
             if (box_entry(gl, o, d, tin, tout)) {
-                tau_star = (float)(-log((double)rng.u()));
+                ts = (double)(float)(-log((double)rng.u()));
                 // voxel coordinates of the first step's nominal centre and the
                 // per-step increment; the step count and the last step's length
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const float pin = o[a] + d[a] * tin;
                     G[a] = (d[a] * gl.inv_h) * p.step;
-                    q[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                    c0[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                    q[a] = c0[a] + 0.0f * G[a];
+                    ig[a] = 1.0f / G[a];
                 }
                 const float len = tout - tin;
                 nsteps = step_count(len, p.step);
                 last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
-                tau = 0.0f;
+                tau = 0.0;
                 k = 0;
                 flying = true;
                 if (STATS) ++st[kStFlights];
@@ -481,76 +500,184 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         }
         // ---- 5. march until `event_batch` lanes wait for an event (or none flies).
         //         Each group issues the voxel loads of kPrefetch consecutive steps
-        //         (advancing the step centre by repeated addition), then consumes
-        //         them in order without branches: tau and the step index advance by
-        //         selection, the step that reaches tau* is recorded, and the
-        //         interaction point is computed once after the group.  A lane whose
-        //         flight ends inside the group no longer needs its step centre.
+        //         (step centres re-anchored every 4 steps, added up in between),
+        //         together with the uniform-cell word at the centre after the
+        //         group, then consumes the steps in order without branches: the
+        //         optical depth (fp64, exact) and the step index advance by
+        //         selection and the step that reaches tau* is recorded.  After the
+        //         group: the interaction or exit, or, for a lane that goes on from
+        //         inside a uniform region, the run of identical steps ahead of it
+        //         taken at once.
+        static_assert(kPrefetch % 4 == 0, "groups hold whole anchor periods");
         for (;;) {
             if (!__any(flying)) break;
             if (__popcll(__ballot(alive && !flying)) >= (unsigned)p.event_batch) break;
             if (!flying) continue;
+            const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
+            const bool skips = lane_pal && gl.cells != nullptr;
+            const float kf = (float)k;
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
-                const uint32_t ix = voxel_index(q[0], gl.cmax[0]);
-                const uint32_t iy = voxel_index(q[1], gl.cmax[1]);
-                const uint32_t iz = voxel_index(q[2], gl.cmax[2]);
-                const uint32_t off = brick_offset(gl, ix, iy, iz);
-                code[u] = gl.vox[off];
-                if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+                if (u % 4 == 0 && u > 0) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+                    for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)u) * G[a];
+                }
+                const uint32_t off = brick_offset(gl, voxel_index(q[0], gl.cmax[0]),
+                                                  voxel_index(q[1], gl.cmax[1]),
+                                                  voxel_index(q[2], gl.cmax[2]));
+                code[u] = gl.vox[off];
+                vr[u] = 0.0f;
+                if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+                if (u % 4 != 3) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+                }
+            }
+            // the anchor after the group and its uniform-cell word
+#pragma unroll
+            for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)kPrefetch) * G[a];
+            uint32_t cell = 0, cx = 0, cy = 0, cz = 0;
+            if (skips) {
+                cx = voxel_index(q[0], gl.cmax[0]) >> kCellLog;
+                cy = voxel_index(q[1], gl.cmax[1]) >> kCellLog;
+                cz = voxel_index(q[2], gl.cmax[2]) >> kCellLog;
+                cell = gl.cells[__umul24(__umul24(cz, (uint32_t)gl.ncy) + cy, (uint32_t)gl.ncx) +
+                                cx];
             }
             const uint32_t rem = nsteps - k;   // steps left in this flight
             const int lay = BATCH ? gl.layout : MODE;
             bool act = true, hit = false, out = false;
-            float mu_hit = 1.0f;
+            double inc_hit = 1.0;
             uint32_t code_hit = 0;
+            // the steps in order; inc_of(u) is the optical-depth increment of
+            // step u.  One copy of the loop per way of finding it, chosen once
+            // per group, keeps the per-step code free of layout branches.
+            auto consume = [&](auto inc_of) {
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
-                float mu;
-                if (lay == kPaletteLane)   // one 24-bit multiply-add for the LDS address
-                    mu = *(const float *)((const char *)mu_pal + __umul24(code[u], bs4));
-                else if (lay == kPaletteShared)
-                    mu = BATCH ? gl.pal_rho[code[u]] * mm[gl.pal_id[code[u]] * bs]
-                               : s_pal_rho[code[u]] * mm[s_pal_id[code[u]] * bs];
-                else
-                    mu = vr[u] * mm[code[u] * bs];
-                const bool inside = (uint32_t)u < rem;
-                const float dk = (uint32_t)(u + 1) == rem ? last : p.step;
-                const float tn = tau + mu * dk;
-                const bool step = act && inside;
-                const bool reach = step && (tn >= tau_star);
-                if (DEBUG) h_steps += step ? 1u : 0u;
-                if (STATS) st[kStSteps] += step ? 1ull : 0ull;
-                out = out || (act && !inside);
-                hit = hit || reach;
-                mu_hit = reach ? mu : mu_hit;
-                code_hit = reach ? code[u] : code_hit;
-                const bool adv = step && !reach;
-                tau = adv ? tn : tau;
-                k += adv ? 1u : 0u;
-                act = adv;
+                for (int u = 0; u < kPrefetch; ++u) {
+                    const double inc = inc_of(u);
+                    const bool inside = (uint32_t)u < rem;
+                    const double tn = tau + inc;
+                    const bool step = act && inside;
+                    const bool reach = step && (tn >= ts);
+                    if (DEBUG) h_steps += step ? 1u : 0u;
+                    if (STATS) st[kStSteps] += step ? 1ull : 0ull;
+                    out = out || (act && !inside);
+                    hit = hit || reach;
+                    inc_hit = reach ? inc : inc_hit;
+                    code_hit = reach ? code[u] : code_hit;
+                    const bool adv = step && !reach;
+                    tau = adv ? tn : tau;
+                    k += adv ? 1u : 0u;
+                    act = adv;
+                }
+            };
+            if (lay == kPaletteLane) {
+                // one 24-bit multiply-add for the LDS address
+                consume([&](int u) -> double {
+                    return *(const double *)((const char *)inc_pal + __umul24(code[u], bs8));
+                });
+            } else {
+                // density and material of the voxel: the gathered density and
+                // code (generic layout), replaced by the palette entry's
+                consume([&](int u) -> double {
+                    float rho = vr[u];
+                    uint32_t id = code[u];
+                    if (lay == kPaletteShared) {
+                        rho = BATCH ? gl.pal_rho[code[u]] : s_pal_rho[code[u]];
+                        id = BATCH ? gl.pal_id[code[u]] : s_pal_id[code[u]];
+                    }
+                    const float mu = rho * mm[id * bs];
+                    return __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
+                });
             }
-            if (hit) {
-                const float a0 = (float)k * p.step;
-                const float si = a0 + (tau_star - tau) / mu_hit;
+            auto interact = [&](uint32_t c, double inc, float len) {
+                // the point where the optical depth reaches tau* inside step k
+                const float si = (float)k * p.step + (float)((ts - tau) / inc * (double)len);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const float pin = o[a] + d[a] * tin;
                     o[a] = pin + d[a] * si;
                 }
                 if (lay == kGeneric)
-                    mat = (int)code_hit;
+                    mat = (int)c;
                 else
-                    mat = BATCH ? (int)gl.pal_id[code_hit] : (int)s_pal_id[code_hit];
+                    mat = BATCH ? (int)gl.pal_id[c] : (int)s_pal_id[c];
                 event = 1;
                 flying = false;
+            };
+            if (hit) {
+                if (k + 1u == nsteps) {
+                    // the last step is shorter: its increment is scaled, and the
+                    // photon may leave the object instead
+                    double r = (double)last / (double)p.step;
+                    r = r > 1.0 ? 1.0 : r;
+                    const double inc_l = on_grid(inc_hit * r);
+                    if (tau + inc_l >= ts) {
+                        interact(code_hit, inc_l, last);
+                    } else {
+                        event = 2;
+                        flying = false;
+                    }
+                } else {
+                    interact(code_hit, inc_hit, p.step);
+                }
             } else if (out) {
                 event = 2;
                 flying = false;
+            } else if (skips && (cell >> 8) != 0u && k + 1u < nsteps) {
+                // the centre q of step k lies in a uniform region: the cube of
+                // cells of radius (cell >> 8) - 1 around (cx, cy, cz).  Count the
+                // steps whose centres stay a margin inside it (the centres are
+                // monotone along each axis), leave out the last step, and take
+                // them at once in multiples of 4.
+                const int r = (int)(cell >> 8);
+                const uint32_t cc[3] = {cx, cy, cz};
+                float n = 4194304.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool neg = (__float_as_uint(G[a]) >> 31) != 0u;
+                    const float bound =
+                        neg ? (float)(((int)cc[a] - r + 1) * (1 << kCellLog)) + kSkipMargin
+                            : (float)(((int)cc[a] + r) * (1 << kCellLog)) - kSkipMargin;
+                    n = fminf(n, fmaxf((bound - q[a]) * ig[a], 0.0f));
+                }
+                uint32_t cnt = (uint32_t)n;
+                const uint32_t avail = nsteps - 1u - k;
+                cnt = (cnt < avail ? cnt : avail) & ~3u;
+                if (cnt >= kMinSkip) {
+                    const uint32_t c = cell & 0xFFu;
+                    const double inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
+                    const double tn = tau + (double)cnt * inc;
+                    if (tn >= ts) {
+                        // the first step of the run whose end reaches tau*
+                        uint32_t j = (uint32_t)fmin(fmax(ceil((ts - tau) / inc) - 1.0, 0.0),
+                                                    (double)(cnt - 1u));
+                        while (j > 0u && tau + (double)j * inc >= ts) --j;
+                        while (tau + (double)(j + 1u) * inc < ts) ++j;
+                        if (DEBUG) h_steps += j + 1u;
+                        if (STATS) {
+                            st[kStSteps] += j + 1u;
+                            st[kStSkipped] += j + 1u;
+                        }
+                        tau = tau + (double)j * inc;
+                        k += j;
+                        interact(c, inc, p.step);
+                    } else {
+                        if (DEBUG) h_steps += cnt;
+                        if (STATS) {
+                            st[kStSteps] += cnt;
+                            st[kStSkipped] += cnt;
+                        }
+                        tau = tn;
+                        k += cnt;
+                        const float kn = (float)k;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) q[a] = c0[a] + kn * G[a];
+                    }
+                }
             }
         }
     }
@@ -577,7 +704,7 @@ __global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
     const int lane = (int)__lane_id();
     const VoxelGrid &gl = p.G;
     bool alive = false, exhausted = false;
-    float q[3] = {0.0f, 0.0f, 0.0f}, G[3] = {0.0f, 0.0f, 0.0f};
+    float c0[3] = {0.0f, 0.0f, 0.0f}, q[3] = {0.0f, 0.0f, 0.0f}, G[3] = {0.0f, 0.0f, 0.0f};
     uint32_t k = 0, nsteps = 0;
     unsigned long long acc = 0, taken = 0;
     for (;;) {
@@ -607,7 +734,8 @@ __global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
                         for (int a = 0; a < 3; ++a) {
                             const float pin = o[a] + d[a] * tin;
                             G[a] = (d[a] * gl.inv_h) * p.step;
-                            q[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                            c0[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                            q[a] = c0[a] + 0.0f * G[a];
                         }
                         nsteps = step_count(tout - tin, p.step);
                         k = 0;
@@ -623,16 +751,25 @@ __global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
         if (alive) {
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
+            const float kf = (float)k;
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
+                if (u % 4 == 0 && u > 0) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)u) * G[a];
+                }
                 const uint32_t off = brick_offset(gl, voxel_index(q[0], gl.cmax[0]),
                                                   voxel_index(q[1], gl.cmax[1]),
                                                   voxel_index(q[2], gl.cmax[2]));
                 code[u] = gl.vox[off];
                 if (MODE == kGeneric) vr[u] = gl.vrho[off];
+                if (u % 4 != 3) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+                    for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+                }
             }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)kPrefetch) * G[a];
             const uint32_t rem = nsteps - k;
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
@@ -673,13 +810,15 @@ __global__ void sample_kernel(const KParams p, int process, int material, float 
 }
 
 size_t transport_lds_bytes(const KParams &p, int layout, int block) {
-    const int cols = p.n_mat + (layout == kPaletteLane ? p.G.n_pal : 0);
-    return (size_t)(kLdsHeader + cols * block) * sizeof(float);
+    const int pal = layout == kPaletteLane ? p.G.n_pal : 0;
+    return (size_t)(kLdsHeader + p.n_mat * block) * sizeof(float) +
+           (size_t)pal * block * sizeof(double);
 }
 
 // batches keep a per-lane palette table as large as the largest per-lane palette
 size_t batch_lds_bytes(const KParams &p, int max_lane_palette, int block) {
-    return (size_t)(kLdsHeader + (p.n_mat + max_lane_palette) * block) * sizeof(float);
+    return (size_t)(kLdsHeader + p.n_mat * block) * sizeof(float) +
+           (size_t)max_lane_palette * block * sizeof(double);
 }
 
 template <int MODE>

@@ -32,7 +32,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
-           "mc_march_probe_async"]
+           "mc_march_probe_async", "mc_cell_map"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -73,7 +73,7 @@ class mc_conv3x3(C.Structure):
 class mc_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "histories", "steps", "flights", "photo", "rayleigh", "compton",
-        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits")]
+        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits", "skipped_steps")]
 
 
 class MCXError(RuntimeError):
@@ -107,6 +107,7 @@ def load():
         "mc_project_async": ([P, F, U64, U64, P, P, P], I),
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
         "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
+        "mc_cell_map": ([P, I, I, I, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
         "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
         "mc_set_stats": ([P, I], I),
@@ -249,6 +250,17 @@ def mc_project(ctx, angle, n_photons, seed, primary, scatter):
 def mc_project_async(ctx, angle, n_photons, seed, d_primary, d_scatter, stream=None):
     _check(ctx, load().mc_project_async(ctx, angle, n_photons, seed, _dev(d_primary),
                                         _dev(d_scatter), _stream(stream)))
+
+
+def mc_cell_map(codes):
+    """codes: uint8 [nz, ny, nx] -> uint16 cell words [ceil(nz/8), ceil(ny/8), ceil(nx/8)]."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    nz, ny, nx = codes.shape
+    out = np.zeros(((nz + 7) // 8, (ny + 7) // 8, (nx + 7) // 8), np.uint16)
+    rc = load().mc_cell_map(_np(codes), nx, ny, nz, _np(out))
+    if rc:
+        raise MCXError(rc, "bad cell-map arguments")
+    return out
 
 
 def mc_march_probe_async(ctx, angle, n_rays, seed, refill_batch, d_sum, stream=None):

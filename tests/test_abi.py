@@ -131,3 +131,48 @@ def test_tables_custom_materials_and_eta(host_ctx):
     ref = o.tables(3)
     for g, r in zip(got, ref):
         assert np.array_equal(g.view(np.uint32), r.view(np.uint32))
+
+
+def brute_cell_map(codes):
+    """Radius of each uniform 8^3 cell by direct search over growing cubes."""
+    nz, ny, nx = codes.shape
+    cz, cy, cx = (nz + 7) // 8, (ny + 7) // 8, (nx + 7) // 8
+    code = np.full((cz, cy, cx), -1)
+    for z in range(cz):
+        for y in range(cy):
+            for x in range(cx):
+                blk = codes[8 * z:8 * z + 8, 8 * y:8 * y + 8, 8 * x:8 * x + 8]
+                if (blk == blk.flat[0]).all():
+                    code[z, y, x] = blk.flat[0]
+    out = np.zeros((cz, cy, cx), np.int64)
+    for z in range(cz):
+        for y in range(cy):
+            for x in range(cx):
+                c = code[z, y, x]
+                if c < 0:
+                    continue
+                r = 1
+                while r < 255:
+                    sl = code[max(z - r, 0):z + r + 1, max(y - r, 0):y + r + 1,
+                              max(x - r, 0):x + r + 1]
+                    if not (sl == c).all():
+                        break
+                    r += 1
+                out[z, y, x] = c | (r << 8)
+    return out
+
+
+@pytest.mark.parametrize("shape,seed", [((20, 33, 41), 0), ((64, 64, 64), 1), ((9, 8, 70), 2)])
+def test_cell_map_matches_brute_force(lib, shape, seed):
+    rng = np.random.default_rng(seed)
+    codes = np.zeros(shape, np.uint8)
+    # a few boxes of other codes in a background of code 0, and one noisy corner
+    for _ in range(4):
+        lo = [int(rng.integers(0, s)) for s in shape]
+        hi = [min(s, l + int(rng.integers(1, 24))) for s, l in zip(shape, lo)]
+        codes[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = rng.integers(1, 5)
+    codes[:5, :5, :5] = rng.integers(0, 3, size=(5, 5, 5))
+    got = mcx.mc_cell_map(codes).astype(np.int64)
+    assert np.array_equal(got, brute_cell_map(codes))
+    uniform = mcx.mc_cell_map(np.full((16, 24, 8), 7, np.uint8))
+    assert np.all(uniform == (7 | (255 << 8)))

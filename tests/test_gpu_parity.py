@@ -226,8 +226,9 @@ def test_stats_match_oracle(gpu):
     o.project(0.0, 200_000, 2)
     so = o.stats()
     say("stats", sg, so)
-    for k in sg:
+    for k in so:
         assert abs(sg[k] - so[k]) <= max(2, 1e-3 * so[k]), k
+    assert 0 <= sg["skipped_steps"] <= sg["steps"]
 
 
 def test_errors(gpu):
