@@ -93,6 +93,23 @@ hipError_t launch_upsample(const float *in, float *out, int nx, int ny, int f, h
     return hipGetLastError();
 }
 
+// out[y][x] = in[flip_y ? ny-1-y : y][flip_x ? nx-1-x : x] (mirror images of a
+// map; training pairs are augmented with them)
+__global__ void flip2d_kernel(const float *in, float *out, int nx, int ny, int fx, int fy) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    const int sx = fx ? nx - 1 - x : x, sy = fy ? ny - 1 - y : y;
+    out[(size_t)y * nx + x] = in[(size_t)sy * nx + sx];
+}
+
+hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(flip2d_kernel, dim3((nx + 255) / 256, ny), dim3(256), 0, s, in, out, nx,
+                       ny, fx, fy);
+    return hipGetLastError();
+}
+
 hipError_t launch_tally_to_float(const int64_t *in, float *out, uint64_t n, double scale,
                                  hipStream_t s) {
     uint64_t grid = (n + 255) / 256;

@@ -231,7 +231,8 @@ __device__ __forceinline__ double on_grid(double x) {
 }
 
 constexpr float kSkipMargin = 1.0f / 64.0f;   // voxels kept from a uniform region's faces
-constexpr uint32_t kMinSkip = 8;             // shortest run taken at once
+constexpr uint32_t kMinSkip = 4;             // shortest run taken at once
+
 
 #ifndef MCX_PREFETCH
 #define MCX_PREFETCH 8
@@ -275,6 +276,14 @@ __device__ __forceinline__ uint32_t voxel_index(float c, float cmax) {
     return (uint32_t)__builtin_amdgcn_fmed3f(c, 0.0f, cmax);
 }
 
+// uniform-cell word of the cell holding the (clamped) voxel of centre q
+__device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[3]) {
+    const uint32_t cx = voxel_index(q[0], g.cmax[0]) >> kCellLog;
+    const uint32_t cy = voxel_index(q[1], g.cmax[1]) >> kCellLog;
+    const uint32_t cz = voxel_index(q[2], g.cmax[2]) >> kCellLog;
+    return g.cells[__umul24(__umul24(cz, (uint32_t)g.ncy) + cy, (uint32_t)g.ncx) + cx];
+}
+
 // MODE: layout of the single object (ignored for batches, where each lane
 // follows the layout of its own job's object).  BATCH: run the job table.
 template <int MODE, bool BATCH, bool STATS, bool DEBUG>
@@ -315,6 +324,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     float tin = 0.0f, last = 0.0f;
     double tau = 0.0, ts = 0.0;
     uint32_t k = 0, nsteps = 0;
+    uint32_t cellw = 0;   // uniform-cell word at the centre of step k (0: none known)
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
@@ -491,6 +501,8 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 nsteps = step_count(len, p.step);
                 last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
                 tau = 0.0;
+                const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
+                cellw = lane_pal && gl.cells != nullptr ? cell_word(gl, q) : 0u;
                 k = 0;
                 flying = true;
                 if (STATS) ++st[kStFlights];
@@ -499,15 +511,15 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             }
         }
         // ---- 5. march until `event_batch` lanes wait for an event (or none flies).
-        //         Each group issues the voxel loads of kPrefetch consecutive steps
-        //         (step centres re-anchored every 4 steps, added up in between),
-        //         together with the uniform-cell word at the centre after the
-        //         group, then consumes the steps in order without branches: the
-        //         optical depth (fp64, exact) and the step index advance by
-        //         selection and the step that reaches tau* is recorded.  After the
-        //         group: the interaction or exit, or, for a lane that goes on from
-        //         inside a uniform region, the run of identical steps ahead of it
-        //         taken at once.
+        //         A lane whose step centre lies in a uniform region first takes
+        //         the run of identical steps ahead of it at once.  Then each group
+        //         issues the voxel loads of kPrefetch consecutive steps (centres
+        //         re-anchored every 4 steps, added up in between) together with
+        //         the uniform-cell word at the centre after the group, and
+        //         consumes the steps in order without branches: the optical depth
+        //         (fp64, exact) and the step index advance by selection, the step
+        //         that reaches tau* is recorded, and the interaction point or the
+        //         exit follows the group.
         static_assert(kPrefetch % 4 == 0, "groups hold whole anchor periods");
         for (;;) {
             if (!__any(flying)) break;
@@ -515,6 +527,80 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             if (!flying) continue;
             const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
             const bool skips = lane_pal && gl.cells != nullptr;
+            const int lay = BATCH ? gl.layout : MODE;
+            auto interact = [&](uint32_t c, double inc, float len) {
+                // the point where the optical depth reaches tau* inside step k
+                const float si = (float)k * p.step + (float)((ts - tau) / inc * (double)len);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float pin = o[a] + d[a] * tin;
+                    o[a] = pin + d[a] * si;
+                }
+                if (lay == kGeneric)
+                    mat = (int)c;
+                else
+                    mat = BATCH ? (int)gl.pal_id[c] : (int)s_pal_id[c];
+                event = 1;
+                flying = false;
+            };
+            // a lane whose step centre lies in a uniform region takes the run of
+            // identical steps ahead of it at once: the cube of cells of radius
+            // (cellw >> 8) - 1 around the centre's cell.  Count the steps whose
+            // centres stay a margin inside it (the centres are monotone along
+            // each axis), leave out the last step, and take them in multiples
+            // of 4; a hit inside the run is found exactly.
+            if (skips && (cellw >> 8) != 0u && k + 1u < nsteps) {
+                const uint32_t cell = cellw;
+                cellw = 0u;
+                const uint32_t cc[3] = {voxel_index(q[0], gl.cmax[0]) >> kCellLog,
+                                        voxel_index(q[1], gl.cmax[1]) >> kCellLog,
+                                        voxel_index(q[2], gl.cmax[2]) >> kCellLog};
+                const int r = (int)(cell >> 8);
+                float n = 4194304.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool neg = (__float_as_uint(G[a]) >> 31) != 0u;
+                    const float bound =
+                        neg ? (float)(((int)cc[a] - r + 1) * (1 << kCellLog)) + kSkipMargin
+                            : (float)(((int)cc[a] + r) * (1 << kCellLog)) - kSkipMargin;
+                    n = fminf(n, fmaxf((bound - q[a]) * ig[a], 0.0f));
+                }
+                uint32_t cnt = (uint32_t)n;
+                const uint32_t avail = nsteps - 1u - k;
+                cnt = (cnt < avail ? cnt : avail) & ~3u;
+                if (cnt >= kMinSkip) {
+                    const uint32_t c = cell & 0xFFu;
+                    const double inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
+                    const double tn = tau + (double)cnt * inc;
+                    if (tn >= ts) {
+                        // the first step of the run whose end reaches tau*
+                        uint32_t j = (uint32_t)fmin(fmax(ceil((ts - tau) / inc) - 1.0, 0.0),
+                                                    (double)(cnt - 1u));
+                        while (j > 0u && tau + (double)j * inc >= ts) --j;
+                        while (tau + (double)(j + 1u) * inc < ts) ++j;
+                        if (DEBUG) h_steps += j + 1u;
+                        if (STATS) {
+                            st[kStSteps] += j + 1u;
+                            st[kStSkipped] += j + 1u;
+                        }
+                        tau = tau + (double)j * inc;
+                        k += j;
+                        interact(c, inc, p.step);
+                    } else {
+                        if (DEBUG) h_steps += cnt;
+                        if (STATS) {
+                            st[kStSteps] += cnt;
+                            st[kStSkipped] += cnt;
+                        }
+                        tau = tn;
+                        k += cnt;
+                        const float kn = (float)k;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) q[a] = c0[a] + kn * G[a];
+                    }
+                }
+            }
+            if (!flying) continue;   // the run held the interaction
             const float kf = (float)k;
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
@@ -538,16 +624,8 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             // the anchor after the group and its uniform-cell word
 #pragma unroll
             for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)kPrefetch) * G[a];
-            uint32_t cell = 0, cx = 0, cy = 0, cz = 0;
-            if (skips) {
-                cx = voxel_index(q[0], gl.cmax[0]) >> kCellLog;
-                cy = voxel_index(q[1], gl.cmax[1]) >> kCellLog;
-                cz = voxel_index(q[2], gl.cmax[2]) >> kCellLog;
-                cell = gl.cells[__umul24(__umul24(cz, (uint32_t)gl.ncy) + cy, (uint32_t)gl.ncx) +
-                                cx];
-            }
+            cellw = skips ? cell_word(gl, q) : 0u;
             const uint32_t rem = nsteps - k;   // steps left in this flight
-            const int lay = BATCH ? gl.layout : MODE;
             bool act = true, hit = false, out = false;
             double inc_hit = 1.0;
             uint32_t code_hit = 0;
@@ -593,21 +671,6 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     return __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
                 });
             }
-            auto interact = [&](uint32_t c, double inc, float len) {
-                // the point where the optical depth reaches tau* inside step k
-                const float si = (float)k * p.step + (float)((ts - tau) / inc * (double)len);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float pin = o[a] + d[a] * tin;
-                    o[a] = pin + d[a] * si;
-                }
-                if (lay == kGeneric)
-                    mat = (int)c;
-                else
-                    mat = BATCH ? (int)gl.pal_id[c] : (int)s_pal_id[c];
-                event = 1;
-                flying = false;
-            };
             if (hit) {
                 if (k + 1u == nsteps) {
                     // the last step is shorter: its increment is scaled, and the
@@ -627,57 +690,6 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             } else if (out) {
                 event = 2;
                 flying = false;
-            } else if (skips && (cell >> 8) != 0u && k + 1u < nsteps) {
-                // the centre q of step k lies in a uniform region: the cube of
-                // cells of radius (cell >> 8) - 1 around (cx, cy, cz).  Count the
-                // steps whose centres stay a margin inside it (the centres are
-                // monotone along each axis), leave out the last step, and take
-                // them at once in multiples of 4.
-                const int r = (int)(cell >> 8);
-                const uint32_t cc[3] = {cx, cy, cz};
-                float n = 4194304.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const bool neg = (__float_as_uint(G[a]) >> 31) != 0u;
-                    const float bound =
-                        neg ? (float)(((int)cc[a] - r + 1) * (1 << kCellLog)) + kSkipMargin
-                            : (float)(((int)cc[a] + r) * (1 << kCellLog)) - kSkipMargin;
-                    n = fminf(n, fmaxf((bound - q[a]) * ig[a], 0.0f));
-                }
-                uint32_t cnt = (uint32_t)n;
-                const uint32_t avail = nsteps - 1u - k;
-                cnt = (cnt < avail ? cnt : avail) & ~3u;
-                if (cnt >= kMinSkip) {
-                    const uint32_t c = cell & 0xFFu;
-                    const double inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
-                    const double tn = tau + (double)cnt * inc;
-                    if (tn >= ts) {
-                        // the first step of the run whose end reaches tau*
-                        uint32_t j = (uint32_t)fmin(fmax(ceil((ts - tau) / inc) - 1.0, 0.0),
-                                                    (double)(cnt - 1u));
-                        while (j > 0u && tau + (double)j * inc >= ts) --j;
-                        while (tau + (double)(j + 1u) * inc < ts) ++j;
-                        if (DEBUG) h_steps += j + 1u;
-                        if (STATS) {
-                            st[kStSteps] += j + 1u;
-                            st[kStSkipped] += j + 1u;
-                        }
-                        tau = tau + (double)j * inc;
-                        k += j;
-                        interact(c, inc, p.step);
-                    } else {
-                        if (DEBUG) h_steps += cnt;
-                        if (STATS) {
-                            st[kStSteps] += cnt;
-                            st[kStSkipped] += cnt;
-                        }
-                        tau = tn;
-                        k += cnt;
-                        const float kn = (float)k;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) q[a] = c0[a] + kn * G[a];
-                    }
-                }
             }
         }
     }

@@ -32,7 +32,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
-           "mc_march_probe_async", "mc_cell_map"]
+           "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -108,6 +108,7 @@ def load():
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
         "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
         "mc_cell_map": ([P, I, I, I, P], I),
+        "mc_flip2d_async": ([P, P, P, I, I, I, I, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
         "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
         "mc_set_stats": ([P, I], I),
@@ -351,6 +352,11 @@ def mc_savgol_async(ctx, d_in, d_out, d_tmp, nx, ny, window, order, stream=None)
 def mc_upsample_cubic_async(ctx, d_in, d_out, nx, ny, factor, stream=None):
     _check(ctx, load().mc_upsample_cubic_async(ctx, _dev(d_in), _dev(d_out), nx, ny, factor,
                                                _stream(stream)))
+
+
+def mc_flip2d_async(ctx, d_in, d_out, nx, ny, flip_x, flip_y, stream=None):
+    _check(ctx, load().mc_flip2d_async(ctx, _dev(d_in), _dev(d_out), nx, ny, int(flip_x),
+                                       int(flip_y), _stream(stream)))
 
 
 def mc_savgol_weights(window, order):

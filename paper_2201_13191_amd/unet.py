@@ -156,6 +156,23 @@ class UNet:
         mcx.mc_nn_pack_channel_async(self.ctx, primary.contiguous(), npix, scale_p, A, 16, 1,
                                      self.stream)
 
+    def set_input_samples(self, scatter, primary, scale_s=1.0, scale_p=1.0):
+        """scatter, primary: sequences of N fp32 device tensors [S,S]; sample i
+        is packed into batch slot i."""
+        A = self.A["x"]
+        npix = self.S * self.S
+        for i in range(self.N):
+            mcx.mc_nn_pack_channel_async(self.ctx, scatter[i], npix, scale_s, A[i], 16, 0,
+                                         self.stream)
+            mcx.mc_nn_pack_channel_async(self.ctx, primary[i], npix, scale_p, A[i], 16, 1,
+                                         self.stream)
+
+    def set_target_samples(self, targets):
+        """targets: sequence of N fp32 device tensors [2S,2S] (copied into place)."""
+        n = 4 * self.S * self.S
+        for i in range(self.N):
+            self.target[i * n:(i + 1) * n].copy_(targets[i].reshape(-1))
+
     def forward(self):
         A = self.A
         self._conv("e1a", A["x"], 0, A["e1a"], 0)
@@ -269,6 +286,15 @@ class UNet:
     def train_step(self, scatter, primary, target, scale_s=1.0, scale_p=1.0):
         self.set_input(scatter, primary, scale_s, scale_p)
         self.target.copy_(target.reshape(-1))
+        self._step()
+
+    def train_step_samples(self, scatter, primary, targets):
+        """One step on N samples given as sequences of per-sample tensors."""
+        self.set_input_samples(scatter, primary)
+        self.set_target_samples(targets)
+        self._step()
+
+    def _step(self):
         self.forward()
         self.loss_and_grad()
         self.backward()

@@ -58,3 +58,20 @@ def test_tally_to_float(env):
     mcx.mc_tally_to_float_async(ctx, d_in, d_out, 5, 2.0 ** -20)
     torch.cuda.synchronize()
     assert np.array_equal(d_out.cpu().numpy(), (v.astype(np.float64) * 2.0 ** -20).astype(np.float32))
+
+
+@pytest.mark.parametrize("ny,nx", [(1, 1), (7, 300), (128, 128)])
+def test_flip2d(env, ny, nx):
+    torch, ctx = env
+    say("flip2d", ny, nx)
+    a = np.random.default_rng(nx).normal(size=(ny, nx)).astype(np.float32)
+    d = torch.from_numpy(a).cuda()
+    out = torch.empty_like(d)
+    for fx in (0, 1):
+        for fy in (0, 1):
+            mcx.mc_flip2d_async(ctx, d, out, nx, ny, fx, fy)
+            torch.cuda.synchronize()
+            ref = a[::-1 if fy else 1, ::-1 if fx else 1]
+            assert np.array_equal(out.cpu().numpy(), ref)
+    with pytest.raises(mcx.MCXError):
+        mcx.mc_flip2d_async(ctx, d, d, nx, ny, 1, 0)
