@@ -49,8 +49,8 @@ __device__ __forceinline__ float unit_float(uint32_t x) {
 struct PhotonStream {
     uint32_t id_lo, id_hi, key0, key1;
     uint32_t next;     // index of the next draw
-    uint32_t cached;   // block index held in blk
-    uint4 blk;
+    uint32_t cached;   // block index held in w0 .. w3
+    uint32_t w0, w1, w2, w3;
 
     __device__ void reset(uint64_t photon, uint32_t k0, uint32_t k1) {
         id_lo = (uint32_t)photon;
@@ -63,12 +63,19 @@ struct PhotonStream {
     __device__ uint32_t raw() {
         const uint32_t b = next >> 2;
         if (b != cached) {
-            blk = philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+            const uint4 blk = philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+            w0 = blk.x;
+            w1 = blk.y;
+            w2 = blk.z;
+            w3 = blk.w;
             cached = b;
         }
-        const uint32_t w = next & 3u;
+        // word (next & 3) from all four words and masks: no selected or indexed
+        // access into the stream, which would keep the stream in scratch memory
+        const uint32_t i = next & 3u;
         ++next;
-        return w == 0u ? blk.x : (w == 1u ? blk.y : (w == 2u ? blk.z : blk.w));
+        return (w0 & (0u - (uint32_t)(i == 0u))) | (w1 & (0u - (uint32_t)(i == 1u))) |
+               (w2 & (0u - (uint32_t)(i == 2u))) | (w3 & (0u - (uint32_t)(i == 3u)));
     }
     __device__ float u() { return unit_float(raw()); }
 };
@@ -309,11 +316,38 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         __syncthreads();
     }
 
-    // the lane's voxel object (uniform for a single projection)
-    VoxelGrid gl = p.G;
+    // the lane's voxel object: the kernel's own for a single projection; in a
+    // batch the index of the job's object.  with_grid(active, f) runs f(grid)
+    // for the active lanes once per distinct object among them (almost always
+    // one), with the descriptor read by scalar loads from the constant address
+    // space, so a batch keeps no per-lane copy of it in vector registers.
+    int gi = 0;
+    using ConstWord = const __attribute__((address_space(4))) uint32_t;
+    static_assert(sizeof(VoxelGrid) % 4 == 0, "descriptor copied word by word");
+    auto with_grid = [&](bool active, auto f) __attribute__((always_inline)) {
+        if (!BATCH) {
+            if (active) f(p.G);
+            return;
+        }
+        unsigned long long todo = __ballot(active);
+        while (todo) {
+            const int leader = __ffsll(todo) - 1;
+            const int g = __builtin_amdgcn_readfirstlane(__shfl(gi, leader));
+            const bool mine = active && gi == g;
+            if (mine) {
+                VoxelGrid gs;
+                ConstWord *src = (ConstWord *)(p.grids + g);
+                uint32_t *dst = (uint32_t *)&gs;
+#pragma unroll
+                for (int w = 0; w < (int)(sizeof(VoxelGrid) / 4); ++w) dst[w] = src[w];
+                f(gs);
+            }
+            todo &= ~__ballot(mine);
+        }
+    };
     int job = 0;          // batch: the lane's job
     int cur_job = 0;      // batch: the job this wave refills from
-    auto frame = [&]() -> const ProjFrame & { return BATCH ? p.jobs[job].F : p.F; };
+    auto frame = [&]() __attribute__((always_inline)) -> const ProjFrame & { return BATCH ? p.jobs[job].F : p.F; };
 
     bool alive = false, flying = false, exhausted = false;
     PhotonStream rng;
@@ -325,6 +359,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     double tau = 0.0, ts = 0.0;
     uint32_t k = 0, nsteps = 0;
     uint32_t cellw = 0;   // uniform-cell word at the centre of step k (0: none known)
+    bool stale = true;    // the LDS attenuation tables do not match the energy yet
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
@@ -332,12 +367,12 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
 
     // attenuation at the photon's energy: per material, and the full-step
     // optical-depth increment per palette entry
-    auto refresh_mu = [&](float energy) {
+    auto refresh_mu = [&](float energy, const VoxelGrid &gr) __attribute__((always_inline)) {
         material_mu(p, energy, mm, bs);
         if (BATCH) {
-            if (gl.layout == kPaletteLane)
-                for (int c = 0; c < gl.n_pal; ++c) {
-                    const float mu = gl.pal_rho[c] * mm[gl.pal_id[c] * bs];
+            if (gr.layout == kPaletteLane)
+                for (int c = 0; c < gr.n_pal; ++c) {
+                    const float mu = gr.pal_rho[c] * mm[gr.pal_id[c] * bs];
                     inc_pal[c * bs] = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
                 }
         } else if (MODE == kPaletteLane) {
@@ -348,7 +383,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         }
     };
     // a new photon: energy bin, direction in the cone, position at the source
-    auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1) {
+    auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1) __attribute__((always_inline)) {
         pid = photon;
         rng.reset(pid, k0, k1);
         e = p.e_bin[pick_bin(p, rng.raw())];
@@ -356,7 +391,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         cone_direction(F, rng, d);
 #pragma unroll
         for (int a = 0; a < 3; ++a) o[a] = F.S[a];
-        refresh_mu(e);
+        stale = true;     // tables are rebuilt when the first flight starts
         n_int = 0;
         alive = true;
         flying = false;
@@ -407,7 +442,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     end = 5;
                 } else if (e2 != e) {
                     e = e2;
-                    refresh_mu(e);
+                    stale = true;
                 }
             }
         } else if (event == 2) {
@@ -462,7 +497,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     if (rank < got) {
                         if (BATCH) {
                             job = cur_job;
-                            gl = p.grids[p.jobs[job].grid];
+                            gi = p.jobs[job].grid;
                             birth(base + rank, p.jobs[job].key0, p.jobs[job].key1);
                         } else {
                             birth(p.first + base + rank, p.key0, p.key1);
@@ -482,18 +517,23 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         }
         if (!__any(alive)) break;
 
-        // ---- 4. start flights (new photons and scattered ones)
-        if (alive && !flying && event == 0) {
+        // ---- 4. start flights (new photons and scattered ones); the LDS tables
+        //         are rebuilt first if the energy changed since the last flight
+        with_grid(alive && !flying && event == 0, [&](const VoxelGrid &gr) __attribute__((always_inline)) {
             float tout;
-            if (box_entry(gl, o, d, tin, tout)) {
+            if (box_entry(gr, o, d, tin, tout)) {
+                if (stale) {
+                    refresh_mu(e, gr);
+                    stale = false;
+                }
                 ts = (double)(float)(-log((double)rng.u()));
                 // voxel coordinates of the first step's nominal centre and the
                 // per-step increment; the step count and the last step's length
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const float pin = o[a] + d[a] * tin;
-                    G[a] = (d[a] * gl.inv_h) * p.step;
-                    c0[a] = (pin - gl.lo[a]) * gl.inv_h + 0.5f * G[a];
+                    G[a] = (d[a] * gr.inv_h) * p.step;
+                    c0[a] = (pin - gr.lo[a]) * gr.inv_h + 0.5f * G[a];
                     q[a] = c0[a] + 0.0f * G[a];
                     ig[a] = 1.0f / G[a];
                 }
@@ -501,15 +541,15 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 nsteps = step_count(len, p.step);
                 last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
                 tau = 0.0;
-                const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
-                cellw = lane_pal && gl.cells != nullptr ? cell_word(gl, q) : 0u;
+                const bool lane_pal = BATCH ? gr.layout == kPaletteLane : MODE == kPaletteLane;
+                cellw = lane_pal && gr.cells != nullptr ? cell_word(gr, q) : 0u;
                 k = 0;
                 flying = true;
                 if (STATS) ++st[kStFlights];
             } else {
                 event = 2;
             }
-        }
+        });
         // ---- 5. march until `event_batch` lanes wait for an event (or none flies).
         //         A lane whose step centre lies in a uniform region first takes
         //         the run of identical steps ahead of it at once.  Then each group
@@ -525,10 +565,11 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             if (!__any(flying)) break;
             if (__popcll(__ballot(alive && !flying)) >= (unsigned)p.event_batch) break;
             if (!flying) continue;
+            with_grid(true, [&](const VoxelGrid &gl) __attribute__((always_inline)) {
             const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
             const bool skips = lane_pal && gl.cells != nullptr;
             const int lay = BATCH ? gl.layout : MODE;
-            auto interact = [&](uint32_t c, double inc, float len) {
+            auto interact = [&](uint32_t c, double inc, float len) __attribute__((always_inline)) {
                 // the point where the optical depth reaches tau* inside step k
                 const float si = (float)k * p.step + (float)((ts - tau) / inc * (double)len);
 #pragma unroll
@@ -600,7 +641,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     }
                 }
             }
-            if (!flying) continue;   // the run held the interaction
+            if (!flying) return;   // the run held the interaction
             const float kf = (float)k;
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
@@ -632,7 +673,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             // the steps in order; inc_of(u) is the optical-depth increment of
             // step u.  One copy of the loop per way of finding it, chosen once
             // per group, keeps the per-step code free of layout branches.
-            auto consume = [&](auto inc_of) {
+            auto consume = [&](auto inc_of) __attribute__((always_inline)) {
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) {
                     const double inc = inc_of(u);
@@ -654,13 +695,13 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             };
             if (lay == kPaletteLane) {
                 // one 24-bit multiply-add for the LDS address
-                consume([&](int u) -> double {
+                consume([&](int u) __attribute__((always_inline)) -> double {
                     return *(const double *)((const char *)inc_pal + __umul24(code[u], bs8));
                 });
             } else {
                 // density and material of the voxel: the gathered density and
                 // code (generic layout), replaced by the palette entry's
-                consume([&](int u) -> double {
+                consume([&](int u) __attribute__((always_inline)) -> double {
                     float rho = vr[u];
                     uint32_t id = code[u];
                     if (lay == kPaletteShared) {
@@ -691,6 +732,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 event = 2;
                 flying = false;
             }
+            });
         }
     }
     if (STATS) {
