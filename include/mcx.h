@@ -305,14 +305,15 @@ mc_status mc_savgol_async(mc_ctx *ctx, const float *d_in, float *d_out, float *d
  * [ny*factor][nx*factor].  fp32. */
 mc_status mc_upsample_cubic_async(mc_ctx *ctx, const float *d_in, float *d_out, int nx, int ny,
                                   int factor, void *stream);
-/* Mirror image of an fp32 map [ny][nx] (device, d_out != d_in):
- * d_out[y][x] = d_in[flip_y ? ny-1-y : y][flip_x ? nx-1-x : x].  The
- * geometry of section II-A is symmetric about both panel axes (the panel is
- * centred on the central ray), so mirrored objects give mirrored primary and
- * scatter maps; training pairs for the learned up-sampler are augmented with
- * these flips. */
+/* Mirror image of an fp32 map [ny][nx] (device, d_out != d_in), optionally
+ * accumulated: d_out[y][x] = alpha * d_in[flip_y ? ny-1-y : y][flip_x ? nx-1-x : x]
+ * + beta * d_out[y][x] (d_out is not read when beta is 0).  The geometry of
+ * section II-A is symmetric about both panel axes (the panel is centred on
+ * the central ray), so mirrored objects give mirrored primary and scatter
+ * maps: training pairs for the learned up-sampler are augmented with these
+ * flips, and its predictions for the four mirror images averaged. */
 mc_status mc_flip2d_async(mc_ctx *ctx, const float *d_in, float *d_out, int nx, int ny,
-                          int flip_x, int flip_y, void *stream);
+                          int flip_x, int flip_y, float alpha, float beta, void *stream);
 /* The fp32 Savitzky-Golay weights mc_savgol_async uses (host only). */
 mc_status mc_savgol_weights(int window, int order, float *weights);
 

@@ -93,20 +93,24 @@ hipError_t launch_upsample(const float *in, float *out, int nx, int ny, int f, h
     return hipGetLastError();
 }
 
-// out[y][x] = in[flip_y ? ny-1-y : y][flip_x ? nx-1-x : x] (mirror images of a
-// map; training pairs are augmented with them)
-__global__ void flip2d_kernel(const float *in, float *out, int nx, int ny, int fx, int fy) {
+// out[y][x] = alpha * in[flip_y ? ny-1-y : y][flip_x ? nx-1-x : x] + beta * out[y][x]
+// (mirror images of a map, optionally accumulated; out is not read when beta
+// is 0): training pairs are augmented with them and predictions averaged
+__global__ void flip2d_kernel(const float *in, float *out, int nx, int ny, int fx, int fy,
+                              float alpha, float beta) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx) return;
     const int sx = fx ? nx - 1 - x : x, sy = fy ? ny - 1 - y : y;
-    out[(size_t)y * nx + x] = in[(size_t)sy * nx + sx];
+    const size_t o = (size_t)y * nx + x;
+    const float v = alpha * in[(size_t)sy * nx + sx];
+    out[o] = beta != 0.0f ? v + beta * out[o] : v;
 }
 
-hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy,
-                         hipStream_t s) {
+hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy, float alpha,
+                         float beta, hipStream_t s) {
     hipLaunchKernelGGL(flip2d_kernel, dim3((nx + 255) / 256, ny), dim3(256), 0, s, in, out, nx,
-                       ny, fx, fy);
+                       ny, fx, fy, alpha, beta);
     return hipGetLastError();
 }
 

@@ -37,8 +37,8 @@ hipError_t launch_clear(unsigned long long *a, size_t na, unsigned long long *b,
                         hipStream_t stream);
 hipError_t launch_savgol(const float *in, float *out, float *tmp, int nx, int ny, int window,
                          const float *coeffs, hipStream_t s);
-hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy,
-                         hipStream_t s);
+hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy, float alpha,
+                         float beta, hipStream_t s);
 hipError_t launch_upsample(const float *in, float *out, int nx, int ny, int f, hipStream_t s);
 hipError_t launch_tally_to_float(const int64_t *in, float *out, uint64_t n, double scale,
                                  hipStream_t s);
@@ -1127,14 +1127,16 @@ mc_status mc_upsample_cubic_async(mc_ctx *c, const float *d_in, float *d_out, in
 }
 
 mc_status mc_flip2d_async(mc_ctx *c, const float *d_in, float *d_out, int nx, int ny, int flip_x,
-                          int flip_y, void *stream) {
+                          int flip_y, float alpha, float beta, void *stream) {
     if (!c) return MC_E_INVALID_ARG;
-    if (!d_in || !d_out || d_in == d_out || nx < 1 || ny < 1 || ny > 65535 || nx > (1 << 24))
+    if (!d_in || !d_out || d_in == d_out || nx < 1 || ny < 1 || ny > 65535 || nx > (1 << 24) ||
+        !std::isfinite(alpha) || !std::isfinite(beta))
         return fail(c, MC_E_INVALID_ARG, "flip: bad image (in and out must differ)");
     mc_status rc = use_device(c);
     if (rc) return rc;
     const hipError_t e =
-        launch_flip2d(d_in, d_out, nx, ny, flip_x != 0, flip_y != 0, (hipStream_t)stream);
+        launch_flip2d(d_in, d_out, nx, ny, flip_x != 0, flip_y != 0, alpha, beta,
+                      (hipStream_t)stream);
     return e == hipSuccess ? MC_OK : hip_fail(c, e, "flip");
 }
 

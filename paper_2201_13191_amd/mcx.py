@@ -108,7 +108,7 @@ def load():
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
         "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
         "mc_cell_map": ([P, I, I, I, P], I),
-        "mc_flip2d_async": ([P, P, P, I, I, I, I, P], I),
+        "mc_flip2d_async": ([P, P, P, I, I, I, I, F, F, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
         "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
         "mc_set_stats": ([P, I], I),
@@ -354,9 +354,9 @@ def mc_upsample_cubic_async(ctx, d_in, d_out, nx, ny, factor, stream=None):
                                                _stream(stream)))
 
 
-def mc_flip2d_async(ctx, d_in, d_out, nx, ny, flip_x, flip_y, stream=None):
+def mc_flip2d_async(ctx, d_in, d_out, nx, ny, flip_x, flip_y, alpha=1.0, beta=0.0, stream=None):
     _check(ctx, load().mc_flip2d_async(ctx, _dev(d_in), _dev(d_out), nx, ny, int(flip_x),
-                                       int(flip_y), _stream(stream)))
+                                       int(flip_y), float(alpha), float(beta), _stream(stream)))
 
 
 def mc_savgol_weights(window, order):

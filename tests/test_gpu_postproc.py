@@ -73,5 +73,11 @@ def test_flip2d(env, ny, nx):
             torch.cuda.synchronize()
             ref = a[::-1 if fy else 1, ::-1 if fx else 1]
             assert np.array_equal(out.cpu().numpy(), ref)
+    # accumulate: out = 0.5 * flip(a) + 2 * out, fp32 with separately rounded ops
+    prev = out.cpu().numpy().copy()
+    mcx.mc_flip2d_async(ctx, d, out, nx, ny, 0, 1, alpha=0.5, beta=2.0)
+    torch.cuda.synchronize()
+    ref = np.float32(0.5) * a[::-1, :] + np.float32(2.0) * prev
+    assert np.array_equal(out.cpu().numpy(), ref)
     with pytest.raises(mcx.MCXError):
         mcx.mc_flip2d_async(ctx, d, d, nx, ny, 1, 0)
