@@ -207,7 +207,7 @@ mc_status mc_march_probe_async(mc_ctx *ctx, float angle_rad, uint64_t n_rays, ui
 /* Uniform-cell map of a voxel object, as the march uses it to take runs of
  * identical voxels at once (host only, no context): codes[nz][ny][nx] are
  * per-voxel codes (the palette index of each (material, density) pair);
- * cells[ceil(nz/8)][ceil(ny/8)][ceil(nx/8)] receives, per cube of 8x8x8
+ * cells[ceil(nz/4)][ceil(ny/4)][ceil(nx/4)] receives, per cube of 4x4x4
  * voxels (clipped to the object), code | r << 8 where r >= 1 means that every
  * cell within Chebyshev distance r - 1 (indices clamped to the grid) holds
  * only that code (r capped at 255), and 0 for a cell holding several codes.

@@ -1,4 +1,4 @@
-// Uniform-cell map of a voxel object: for each cube of 8x8x8 voxels, its
+// Uniform-cell map of a voxel object: for each cube of 4x4x4 voxels, its
 // palette code if all its voxels share one, and the Chebyshev radius (in
 // cells) of the cube of cells around it that holds only that code.  The
 // march uses it to take whole runs of steps through identical voxels at

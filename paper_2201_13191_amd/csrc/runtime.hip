@@ -68,7 +68,7 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 48;
+constexpr int kDefaultEventBatch = 52;
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or
@@ -535,7 +535,7 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                                          "distinct (material, density) pairs");
     mc_status rc = use_device(c);
     if (rc) return rc;
-    // bricked host images, and the code of each uniform 8^3 cell (-1: mixed)
+    // bricked host images, and the code of each uniform cell (-1: mixed)
     std::vector<uint8_t> vox(padded, 0);
     std::vector<float> vr;
     if (!palette_ok) vr.assign(padded, 0.0f);

@@ -254,10 +254,10 @@ def mc_project_async(ctx, angle, n_photons, seed, d_primary, d_scatter, stream=N
 
 
 def mc_cell_map(codes):
-    """codes: uint8 [nz, ny, nx] -> uint16 cell words [ceil(nz/8), ceil(ny/8), ceil(nx/8)]."""
+    """codes: uint8 [nz, ny, nx] -> uint16 cell words [ceil(nz/4), ceil(ny/4), ceil(nx/4)]."""
     codes = np.ascontiguousarray(codes, dtype=np.uint8)
     nz, ny, nx = codes.shape
-    out = np.zeros(((nz + 7) // 8, (ny + 7) // 8, (nx + 7) // 8), np.uint16)
+    out = np.zeros(((nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4), np.uint16)
     rc = load().mc_cell_map(_np(codes), nx, ny, nz, _np(out))
     if rc:
         raise MCXError(rc, "bad cell-map arguments")

@@ -133,15 +133,18 @@ def test_tables_custom_materials_and_eta(host_ctx):
         assert np.array_equal(g.view(np.uint32), r.view(np.uint32))
 
 
+CELL = 4   # edge of a uniform cell in voxels
+
+
 def brute_cell_map(codes):
-    """Radius of each uniform 8^3 cell by direct search over growing cubes."""
+    """Radius of each uniform cell by direct search over growing cubes."""
     nz, ny, nx = codes.shape
-    cz, cy, cx = (nz + 7) // 8, (ny + 7) // 8, (nx + 7) // 8
+    cz, cy, cx = -(-nz // CELL), -(-ny // CELL), -(-nx // CELL)
     code = np.full((cz, cy, cx), -1)
     for z in range(cz):
         for y in range(cy):
             for x in range(cx):
-                blk = codes[8 * z:8 * z + 8, 8 * y:8 * y + 8, 8 * x:8 * x + 8]
+                blk = codes[CELL * z:CELL * (z + 1), CELL * y:CELL * (y + 1), CELL * x:CELL * (x + 1)]
                 if (blk == blk.flat[0]).all():
                     code[z, y, x] = blk.flat[0]
     out = np.zeros((cz, cy, cx), np.int64)
