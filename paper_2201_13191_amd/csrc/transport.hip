@@ -34,9 +34,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // each 32x32 -> 64-bit product in one multiply-add (both halves)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     }
     return c;
 }
@@ -78,6 +80,46 @@ struct PhotonStream {
                (w2 & (0u - (uint32_t)(i == 2u))) | (w3 & (0u - (uint32_t)(i == 3u)));
     }
     __device__ float u() { return unit_float(raw()); }
+    // the next N words (N <= 4) with a single block computation: they lie in
+    // the cached block and the one after it, or, from a block boundary, all in
+    // one new block (the cached block always holds the last word drawn)
+    template <int N>
+    __device__ __forceinline__ void draw(uint32_t (&r)[N]) {
+        static_assert(N >= 1 && N <= 4, "one block at most");
+        const uint32_t sh = next & 3u;
+        const uint32_t b0 = next >> 2, b1 = (next + (uint32_t)N - 1u) >> 2;
+        const bool fresh = b0 != cached;
+        const bool straddle = !fresh && b1 != b0;
+        uint32_t x0 = w0, x1 = w1, x2 = w2, x3 = w3;   // the block before the new one
+        if (fresh || straddle) {
+            const uint32_t b = fresh ? b0 : b1;
+            const uint4 blk = philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+            w0 = blk.x;
+            w1 = blk.y;
+            w2 = blk.z;
+            w3 = blk.w;
+            cached = b;
+        }
+        if (!straddle) {
+            x0 = w0;
+            x1 = w1;
+            x2 = w2;
+            x3 = w3;
+        }
+        // words sh .. sh + N - 1 of the window x0 .. x3, w0 .. w3, by a
+        // two-stage shift (by sh & 1, then by sh & 2).  Each stage picks whole
+        // words with a byte permute, which keeps the window in registers
+        // (a select between its elements becomes an indexed scratch access).
+        const uint32_t x[8] = {x0, x1, x2, x3, w0, w1, w2, w3};
+        const uint32_t p1 = (sh & 1u) ? 0x07060504u : 0x03020100u;
+        const uint32_t p2 = (sh & 2u) ? 0x07060504u : 0x03020100u;
+        uint32_t y[N + 2];
+#pragma unroll
+        for (int i = 0; i < N + 2; ++i) y[i] = __builtin_amdgcn_perm(x[i + 1], x[i], p1);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = __builtin_amdgcn_perm(y[i + 2], y[i], p2);
+        next += (uint32_t)N;
+    }
 };
 
 // ------------------------------------------------------------------ tables
@@ -102,46 +144,63 @@ __device__ __forceinline__ void material_mu(const KParams &p, float e, float *mm
 
 // ------------------------------------------------------------------ samplers
 // Kahn's rejection method for the Klein-Nishina polar angle: x = E/E' drawn
-// from one of two branches and accepted against the KN shape.
-__device__ void sample_compton(PhotonStream &s, float e, float &ct, float &e_out) {
+// from one of two branches and accepted against the KN shape.  One trial
+// (three draws); on acceptance the scattered energy and polar cosine are set.
+__device__ __forceinline__ bool compton_trial(PhotonStream &s, float e, float &ct, float &e_out) {
     const double a = (double)e / 510.99895;
     const double top = 1.0 + 2.0 * a;
     const double branch = top / (9.0 + 2.0 * a);
+    uint32_t w[3];
+    s.draw(w);
+    const double r1 = (double)unit_float(w[0]);
+    const double r2 = (double)unit_float(w[1]);
+    const double r3 = (double)unit_float(w[2]);
     double x;
-    for (;;) {
-        const double r1 = (double)s.u();
-        const double r2 = (double)s.u();
-        const double r3 = (double)s.u();
-        if (r1 <= branch) {
-            x = 1.0 + 2.0 * a * r2;
-            if (r3 <= 4.0 * (1.0 / x - 1.0 / (x * x))) break;
-        } else {
-            x = top / (1.0 + 2.0 * a * r2);
-            const double c = 1.0 - (x - 1.0) / a;
-            if (r3 <= 0.5 * (c * c + 1.0 / x)) break;
-        }
+    bool ok;
+    if (r1 <= branch) {
+        x = 1.0 + 2.0 * a * r2;
+        ok = r3 <= 4.0 * (1.0 / x - 1.0 / (x * x));
+    } else {
+        x = top / (1.0 + 2.0 * a * r2);
+        const double c = 1.0 - (x - 1.0) / a;
+        ok = r3 <= 0.5 * (c * c + 1.0 / x);
     }
-    e_out = (float)((double)e / x);
-    ct = (float)(1.0 - (x - 1.0) / a);
+    if (ok) {
+        e_out = (float)((double)e / x);
+        ct = (float)(1.0 - (x - 1.0) / a);
+    }
+    return ok;
+}
+
+__device__ void sample_compton(PhotonStream &s, float e, float &ct, float &e_out) {
+    while (!compton_trial(s, e, ct, e_out)) {
+    }
 }
 
 // Rayleigh polar angle: v = sin^2(theta/2)/lambda^2 inverted from the
 // (1 + b v)^-4 form-factor weight, accepted with (1 + cos^2)/2 evaluated on
-// the fp32 cosine.
-__device__ float sample_rayleigh(PhotonStream &s, float e, double b) {
+// the fp32 cosine.  One trial (two draws); the cosine is set either way.
+__device__ __forceinline__ bool rayleigh_trial(PhotonStream &s, float e, double b, float &cf) {
     const double t = (double)e / 12.398419843320026;
     const double V = t * t;
     const double W = 1.0 + b * V;
     const double ymin = 1.0 / (W * W * W);
-    for (;;) {
-        const double r1 = (double)s.u();
-        const double r2 = (double)s.u();
-        const double y = 1.0 - r1 * (1.0 - ymin);
-        const double v = (1.0 / cbrt(y) - 1.0) / b;
-        const float cf = (float)(1.0 - 2.0 * v / V);
-        const double cd = (double)cf;
-        if (r2 <= 0.5 * (1.0 + cd * cd)) return cf;
+    uint32_t w[2];
+    s.draw(w);
+    const double r1 = (double)unit_float(w[0]);
+    const double r2 = (double)unit_float(w[1]);
+    const double y = 1.0 - r1 * (1.0 - ymin);
+    const double v = (1.0 / cbrt(y) - 1.0) / b;
+    cf = (float)(1.0 - 2.0 * v / V);
+    const double cd = (double)cf;
+    return r2 <= 0.5 * (1.0 + cd * cd);
+}
+
+__device__ float sample_rayleigh(PhotonStream &s, float e, double b) {
+    float cf;
+    while (!rayleigh_trial(s, e, b, cf)) {
     }
+    return cf;
 }
 
 __device__ __forceinline__ void scatter_direction(float &dx, float &dy, float &dz, float ct,
@@ -643,6 +702,13 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             }
             if (!flying) return;   // the run held the interaction
             const float kf = (float)k;
+            // the anchor after the group and its uniform-cell word (loaded
+            // before the group's voxels, so that those are used in the block
+            // that loads them)
+            float qn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) qn[a] = c0[a] + (kf + (float)kPrefetch) * G[a];
+            cellw = skips ? cell_word(gl, qn) : 0u;
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
 #pragma unroll
@@ -662,32 +728,32 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
                 }
             }
-            // the anchor after the group and its uniform-cell word
 #pragma unroll
-            for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)kPrefetch) * G[a];
-            cellw = skips ? cell_word(gl, q) : 0u;
+            for (int a = 0; a < 3; ++a) q[a] = qn[a];
             const uint32_t rem = nsteps - k;   // steps left in this flight
-            bool act = true, hit = false, out = false;
+            bool act = true, hit = false;
             double inc_hit = 1.0;
             uint32_t code_hit = 0;
             // the steps in order; inc_of(u) is the optical-depth increment of
             // step u.  One copy of the loop per way of finding it, chosen once
             // per group, keeps the per-step code free of layout branches.
+            // Steps past the flight's end (u >= rem) are consumed like the
+            // others: their centres are clamped into the grid, and a group that
+            // takes k to nsteps or beyond ends the flight whatever it found
+            // there, so they change nothing but the per-step counts, which the
+            // counting variants keep exact.
             auto consume = [&](auto inc_of) __attribute__((always_inline)) {
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) {
                     const double inc = inc_of(u);
-                    const bool inside = (uint32_t)u < rem;
                     const double tn = tau + inc;
-                    const bool step = act && inside;
-                    const bool reach = step && (tn >= ts);
-                    if (DEBUG) h_steps += step ? 1u : 0u;
-                    if (STATS) st[kStSteps] += step ? 1ull : 0ull;
-                    out = out || (act && !inside);
+                    const bool reach = act && (tn >= ts);
+                    if (DEBUG) h_steps += act && (uint32_t)u < rem ? 1u : 0u;
+                    if (STATS) st[kStSteps] += act && (uint32_t)u < rem ? 1ull : 0ull;
                     hit = hit || reach;
                     inc_hit = reach ? inc : inc_hit;
                     code_hit = reach ? code[u] : code_hit;
-                    const bool adv = step && !reach;
+                    const bool adv = act && !reach;
                     tau = adv ? tn : tau;
                     k += adv ? 1u : 0u;
                     act = adv;
@@ -712,7 +778,11 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     return __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
                 });
             }
-            if (hit) {
+            if (k >= nsteps) {
+                // the flight ended inside the group (or exactly at its end)
+                event = 2;
+                flying = false;
+            } else if (hit) {
                 if (k + 1u == nsteps) {
                     // the last step is shorter: its increment is scaled, and the
                     // photon may leave the object instead
@@ -728,9 +798,6 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 } else {
                     interact(code_hit, inc_hit, p.step);
                 }
-            } else if (out) {
-                event = 2;
-                flying = false;
             }
             });
         }

@@ -27,7 +27,7 @@ def test_autotune_and_cache(tmp_path):
     t = mcx.mc_autotune(g.ctx, 0.2, 200_000, 5, cache)
     say("autotune result", t)
     assert t["from_cache"] == 0 and t["candidates"] == 30 and t["rejected"] == 0
-    assert t["block"] in (64, 128, 256) and 32 <= t["event_batch"] <= 56
+    assert t["block"] in (64, 128, 256) and 40 <= t["event_batch"] <= 60
     p, s = g.project(0.2, 200_000, 5)          # runs with the tuned shape
     assert np.array_equal(p, ref[0]) and np.array_equal(s, ref[1])
     lines = open(cache).read().strip().splitlines()
