@@ -203,9 +203,10 @@ __device__ float sample_rayleigh(PhotonStream &s, float e, double b) {
     return cf;
 }
 
-__device__ __forceinline__ void scatter_direction(float &dx, float &dy, float &dz, float ct,
-                                                  float cp, float sp) {
-    const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+// the direction rotated by polar angle (cosine ct, sine st) and azimuth
+// (cosine cp, sine sp), renormalised
+__device__ __forceinline__ void rotate_direction(float &dx, float &dy, float &dz, float ct,
+                                                 float st, float cp, float sp) {
     float nx, ny, nz;
     if (fabsf(dz) < 0.99999f) {
         const float t = sqrtf(1.0f - dz * dz);
@@ -419,6 +420,14 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     uint32_t k = 0, nsteps = 0;
     uint32_t cellw = 0;   // uniform-cell word at the centre of step k (0: none known)
     bool stale = true;    // the LDS attenuation tables do not match the energy yet
+    // Between flights, three flight variables hold what the next flight
+    // needs, without registers of their own: `last` the polar cosine of the
+    // pending turn (birth: into the cone; scattering: away from the old
+    // direction), `nsteps` the azimuth's draw, and `ts` the draw of the next
+    // flight's optical depth (the word after the azimuth's), as a double.
+    bool turn = false;
+    float &dir_ct = last;
+    uint32_t &phi_w = nsteps;
     int n_int = 0, mat = 0;
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
@@ -445,9 +454,16 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1) __attribute__((always_inline)) {
         pid = photon;
         rng.reset(pid, k0, k1);
-        e = p.e_bin[pick_bin(p, rng.raw())];
+        // the first block: energy bin, the cone's polar cosine and azimuth,
+        // and the first flight's optical depth
+        uint32_t w[4];
+        rng.draw(w);
+        e = p.e_bin[pick_bin(p, w[0])];
         const ProjFrame &F = frame();
-        cone_direction(F, rng, d);
+        dir_ct = 1.0f - unit_float(w[1]) * F.omc;
+        phi_w = w[2];
+        ts = (double)w[3];
+        turn = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) o[a] = F.S[a];
         stale = true;     // tables are rebuilt when the first flight starts
@@ -489,16 +505,21 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     if (STATS) ++st[kStCompt];
                     if (DEBUG && n_int == 0) h_first = 3;
                 }
-                double sphi, cphi;
-                sincos(6.283185307179586 * (double)rng.u(), &sphi, &cphi);
-                scatter_direction(d[0], d[1], d[2], ct, (float)cphi, (float)sphi);
+                uint32_t w[2];
+                rng.draw(w);
+                dir_ct = ct;
+                phi_w = w[0];
+                ts = (double)w[1];
+                turn = true;
                 ++n_int;
                 if (e2 < 1.0f) {
                     if (STATS) ++st[kStCut];
                     end = 4;
+                    turn = false;
                 } else if (n_int >= kMaxScatterings) {
                     if (STATS) ++st[kStCap];
                     end = 5;
+                    turn = false;
                 } else if (e2 != e) {
                     e = e2;
                     stale = true;
@@ -576,6 +597,25 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         }
         if (!__any(alive)) break;
 
+        // ---- 3b. new directions of born and scattered photons, with one
+        //          azimuth evaluation for both
+        if (turn) {
+            turn = false;
+            double sphi, cphi;
+            sincos(6.283185307179586 * (double)unit_float(phi_w), &sphi, &cphi);
+            const float cp = (float)cphi, sp = (float)sphi;
+            const float ct = dir_ct;
+            const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+            if (n_int == 0) {
+                const ProjFrame &F = frame();
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    d[a] = (ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
+            } else {
+                rotate_direction(d[0], d[1], d[2], ct, stt, cp, sp);
+            }
+        }
+
         // ---- 4. start flights (new photons and scattered ones); the LDS tables
         //         are rebuilt first if the energy changed since the last flight
         with_grid(alive && !flying && event == 0, [&](const VoxelGrid &gr) __attribute__((always_inline)) {
@@ -585,7 +625,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     refresh_mu(e, gr);
                     stale = false;
                 }
-                ts = (double)(float)(-log((double)rng.u()));
+                ts = (double)(float)(-log((double)unit_float((uint32_t)ts)));
                 // voxel coordinates of the first step's nominal centre and the
                 // per-step increment; the step count and the last step's length
 #pragma unroll
