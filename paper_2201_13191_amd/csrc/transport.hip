@@ -437,15 +437,17 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     // optical-depth increment per palette entry
     auto refresh_mu = [&](float energy, const VoxelGrid &gr) __attribute__((always_inline)) {
         material_mu(p, energy, mm, bs);
-        if (BATCH) {
-            if (gr.layout == kPaletteLane)
-                for (int c = 0; c < gr.n_pal; ++c) {
-                    const float mu = gr.pal_rho[c] * mm[gr.pal_id[c] * bs];
-                    inc_pal[c * bs] = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
-                }
-        } else if (MODE == kPaletteLane) {
-            for (int c = 0; c < p.G.n_pal; ++c) {
-                const float mu = s_pal_rho[c] * mm[s_pal_id[c] * bs];
+        if (BATCH ? gr.layout == kPaletteLane : MODE == kPaletteLane) {
+            // the palette (the same for every lane) by scalar loads, so each
+            // entry costs one LDS read of the lane's material column; the ids
+            // are read four to a word (the id array holds 256 entries)
+            using ConstF = const __attribute__((address_space(4))) float;
+            using ConstW = const __attribute__((address_space(4))) uint32_t;
+            const ConstF *rho = (const ConstF *)gr.pal_rho;
+            const ConstW *ids = (const ConstW *)gr.pal_id;
+            for (int c = 0; c < gr.n_pal; ++c) {
+                const int id = (int)((ids[c >> 2] >> (8 * (c & 3))) & 0xFFu);
+                const float mu = rho[c] * mm[id * bs];
                 inc_pal[c * bs] = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
             }
         }
@@ -713,9 +715,11 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     const double inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
                     const double tn = tau + (double)cnt * inc;
                     if (tn >= ts) {
-                        // the first step of the run whose end reaches tau*
-                        uint32_t j = (uint32_t)fmin(fmax(ceil((ts - tau) / inc) - 1.0, 0.0),
-                                                    (double)(cnt - 1u));
+                        // the first step of the run whose end reaches tau*:
+                        // an fp32 estimate, made exact by the fp64 checks
+                        const float est = (float)(ts - tau) * __builtin_amdgcn_rcpf((float)inc);
+                        uint32_t j = (uint32_t)fminf(fmaxf(ceilf(est) - 1.0f, 0.0f),
+                                                     (float)(cnt - 1u));
                         while (j > 0u && tau + (double)j * inc >= ts) --j;
                         while (tau + (double)(j + 1u) * inc < ts) ++j;
                         if (DEBUG) h_steps += j + 1u;
