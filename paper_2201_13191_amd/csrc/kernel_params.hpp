@@ -24,6 +24,12 @@ struct ProjFrame {
 // one-byte codes is one 128-byte cache line.
 constexpr int kBx = 8, kBy = 4, kBz = 4;
 constexpr int kBrick = kBx * kBy * kBz;
+// When it fits the 24-bit brick strides, a bricked object extends kEdgePad
+// voxels past its high faces (x, y and z) with copies of the face voxels, so
+// that a centre up to kEdgePad - 1 voxels past a high face, or anywhere below
+// a low face (the float to unsigned conversion saturates at 0), reads the
+// voxel of the clamped centre without a clamp.
+constexpr int kEdgePad = 9;
 // uniform-cell map: cubes of 2^kCellLog voxels per edge (4: measured faster
 // than 2, 8 or 16 on the 256^3 benchmark)
 constexpr int kCellLog = 2;
@@ -55,6 +61,10 @@ struct VoxelGrid {
     // code, 0 for a cell with several codes; null when the march does not skip
     const uint16_t *cells;
     int ncx, ncy;
+    // 1 when the object has its edge copies and a step is at most one voxel:
+    // a group's centres (at most 8 steps past the flight's end) then stay in
+    // the extended grid and its gathers convert them without clamping
+    int unclamped;
 };
 
 // One projection of a batch: its frame, Philox key, photon count, images

@@ -76,6 +76,7 @@ constexpr int kDefaultEventBatch = 56;
 // distinct (id, rho) pairs).
 struct Phantom {
     int nx = 0, ny = 0, nz = 0, nbx = 0, nby = 0, nbz = 0;
+    int edge_pad = 0;   // copies of the face voxels past the high faces (0 or kEdgePad)
     float h = 0.0f;
     int max_id = 0;
     bool generic = false;
@@ -294,6 +295,7 @@ VoxelGrid grid_of(const mc_ctx *c, const Phantom &ph) {
     G.nbx = ph.nbx; G.nby = ph.nby;
     G.ry = (uint32_t)ph.nbx * kBrick - 32u;
     G.rz = (uint32_t)ph.nbx * ph.nby * kBrick - 128u;
+    G.unclamped = ph.edge_pad >= kEdgePad && c->g.step_mm <= ph.h;
     G.cmax[0] = (float)(ph.nx - 1);
     G.cmax[1] = (float)(ph.ny - 1);
     G.cmax[2] = (float)(ph.nz - 1);
@@ -484,7 +486,21 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     if (!ids || !rho || nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096 ||
         !(h > 0.0f) || !std::isfinite(h))
         return fail(c, MC_E_INVALID_ARG, "bad phantom dimensions");
-    const int nbx = (nx + kBx - 1) / kBx, nby = (ny + kBy - 1) / kBy, nbz = (nz + kBz - 1) / kBz;
+    // bricks covering the object and, where the 24-bit brick strides allow,
+    // kEdgePad more voxels past each high face
+    auto bricks = [&](int pad, int &bx, int &by, int &bz) {
+        bx = (nx + pad + kBx - 1) / kBx;
+        by = (ny + pad + kBy - 1) / kBy;
+        bz = (nz + pad + kBz - 1) / kBz;
+        return (size_t)bx * by * kBrick - kBrick < ((size_t)1 << 24) &&
+               (size_t)bx * by * bz * kBrick < ((size_t)1 << 31);
+    };
+    int nbx, nby, nbz;
+    int edge_pad = kEdgePad;
+    if (!bricks(edge_pad, nbx, nby, nbz)) {
+        edge_pad = 0;
+        bricks(0, nbx, nby, nbz);
+    }
     const size_t nv = (size_t)nx * ny * nz;
     const size_t padded = (size_t)nbx * nby * nbz * kBrick;
     if (padded >= (size_t)1 << 31) return fail(c, MC_E_INVALID_ARG, "phantom too large (2^31 voxels)");
@@ -576,6 +592,24 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                     cc = -1;
             }
         }
+    if (edge_pad) {
+        // every bricked position past a high face takes the voxel at the
+        // clamped position
+        auto boff = [&](int x, int y, int z) {
+            return (((size_t)(z / kBz) * nby + (y / kBy)) * nbx + x / kBx) * kBrick +
+                   (size_t)(((z % kBz) * kBy + (y % kBy)) * kBx + (x % kBx));
+        };
+        const int X = nbx * kBx, Y = nby * kBy, Z = nbz * kBz;
+        for (int z = 0; z < Z; ++z)
+            for (int y = 0; y < Y; ++y)
+                for (int x = (z < nz && y < ny) ? nx : 0; x < X; ++x) {
+                    const size_t src = boff(std::min(x, nx - 1), std::min(y, ny - 1),
+                                            std::min(z, nz - 1));
+                    const size_t dst = boff(x, y, z);
+                    vox[dst] = vox[src];
+                    if (!palette_ok) vr[dst] = vr[src];
+                }
+    }
     std::vector<uint16_t> cells;
     if (palette_ok) cell_radii(ncx, ncy, ncz, cell_code, cells);
     HIP_TRY(c, hipDeviceSynchronize());
@@ -598,6 +632,7 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     out.ncx = ncx; out.ncy = ncy; out.ncz = ncz;
     out.nx = nx; out.ny = ny; out.nz = nz; out.h = h;
     out.nbx = nbx; out.nby = nby; out.nbz = nbz;
+    out.edge_pad = edge_pad;
     out.max_id = max_id;
     out.generic = !palette_ok;
     out.n_pal = palette_ok ? n_pal : 0;

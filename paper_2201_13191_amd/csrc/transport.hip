@@ -343,6 +343,14 @@ __device__ __forceinline__ uint32_t voxel_index(float c, float cmax) {
     return (uint32_t)__builtin_amdgcn_fmed3f(c, 0.0f, cmax);
 }
 
+// voxel index along one axis without the upper clamp: v_cvt_u32_f32 itself
+// saturates (negative and NaN to 0), which C's conversion does not promise
+__device__ __forceinline__ uint32_t saturated_index(float c) {
+    uint32_t i;
+    asm("v_cvt_u32_f32 %0, %1" : "=v"(i) : "v"(c));
+    return i;
+}
+
 // uniform-cell word of the cell holding the (clamped) voxel of centre q
 __device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[3]) {
     const uint32_t cx = voxel_index(q[0], g.cmax[0]) >> kCellLog;
@@ -755,23 +763,32 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             cellw = skips ? cell_word(gl, qn) : 0u;
             uint32_t code[kPrefetch];
             float vr[kPrefetch];
+            // the group's gathers; with the object's edge copies (and steps of
+            // at most a voxel) the coordinates need no clamp, one copy of the
+            // loop per case under a branch that is uniform across the wave
+            auto gather = [&](auto index) __attribute__((always_inline)) {
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
-                if (u % 4 == 0 && u > 0) {
+                for (int u = 0; u < kPrefetch; ++u) {
+                    if (u % 4 == 0 && u > 0) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)u) * G[a];
+                        for (int a = 0; a < 3; ++a) q[a] = c0[a] + (kf + (float)u) * G[a];
+                    }
+                    const uint32_t off = brick_offset(gl, index(q[0], gl.cmax[0]),
+                                                      index(q[1], gl.cmax[1]),
+                                                      index(q[2], gl.cmax[2]));
+                    code[u] = gl.vox[off];
+                    vr[u] = 0.0f;
+                    if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+                    if (u % 4 != 3) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
+                    }
                 }
-                const uint32_t off = brick_offset(gl, voxel_index(q[0], gl.cmax[0]),
-                                                  voxel_index(q[1], gl.cmax[1]),
-                                                  voxel_index(q[2], gl.cmax[2]));
-                code[u] = gl.vox[off];
-                vr[u] = 0.0f;
-                if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
-                if (u % 4 != 3) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
-                }
-            }
+            };
+            if (gl.unclamped)
+                gather([](float c, float) __attribute__((always_inline)) { return saturated_index(c); });
+            else
+                gather([](float c, float cmax) __attribute__((always_inline)) { return voxel_index(c, cmax); });
 #pragma unroll
             for (int a = 0; a < 3; ++a) q[a] = qn[a];
             const uint32_t rem = nsteps - k;   // steps left in this flight

@@ -117,6 +117,21 @@ def test_cylinder64_workload(gpu):
                     o.debug_histories(0.0, 0, 200_000, 0))
 
 
+def test_step_longer_than_voxel(gpu):
+    """Steps of 1.6 voxels: the gathers clamp their coordinates (the edge copies
+    past the high faces cover steps of at most one voxel)."""
+    rng = np.random.default_rng(11)
+    ids = rng.integers(0, 5, size=(18, 21, 23)).astype(np.uint8)
+    rho = rng.uniform(0.0, 3.0, size=ids.shape).astype(np.float32)
+    geo = dict(sod_mm=300.0, sdd_mm=700.0, nu=40, nv=30, pu_mm=1.0, pv_mm=1.2, snu=10, snv=5,
+               step_mm=0.8, flags=0)
+    say("random 23x21x18 phantom at 0.5 mm, step 0.8 mm, 200003 photons")
+    o, g = pair(ids, rho, 0.5, geo, inputs.kramers_spectrum(150, 2.0))
+    pg, sg = g.project(0.3, 200_003, 5)
+    po, so = o.project(0.3, 200_003, 5, threads=8)
+    check_images("step-over-voxel", pg, sg, po, so)
+
+
 def test_random_phantom_polychromatic_ragged(gpu):
     rng = np.random.default_rng(7)
     ids = rng.integers(0, 5, size=(16, 20, 24)).astype(np.uint8)
