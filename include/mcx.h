@@ -269,6 +269,8 @@ mc_status mc_get_shape(mc_ctx *ctx, int *nx, int *ny, int *nz, int *nu, int *nv,
 /* Result of mc_autotune. */
 typedef struct mc_tuning {
     int32_t block, blocks_per_cu, event_batch;
+    int32_t table_layout;    /* MC_LAYOUT_PALETTE_LANE or _SHARED for palette
+                                objects of <= 32 entries, else the object's own    */
     int32_t from_cache;      /* 1: taken from the cache, nothing was timed          */
     int32_t candidates;      /* launch shapes timed                                 */
     int32_t rejected;        /* shapes whose images differed bitwise (must be 0)    */
@@ -276,13 +278,18 @@ typedef struct mc_tuning {
     double histories_per_s;
 } mc_tuning;
 
-/* Launch-shape autotuner: times block size x blocks per CU x event batch on
- * the context's current object, panel and spectrum (n_photons of projection
- * angle_rad with `seed`), checks that every shape reproduces the first
- * shape's images bitwise (rejecting any that does not), applies the fastest
- * with mc_set_launch and appends it to the JSON-lines file cache_path (may be
- * NULL).  If cache_path already holds an entry for this device and workload
- * class, that entry is applied and nothing is timed.  Uses the GPU. */
+/* Launch-shape autotuner: times block size x blocks per CU x event batch x
+ * attenuation-table layout (per-lane tables of every palette entry, or the
+ * shared palette with per-lane tables per material; both for palette objects
+ * of <= 32 entries) on the context's current object, panel and spectrum
+ * (n_photons of projection angle_rad with `seed`), checks that every
+ * candidate reproduces the first one's images bitwise (rejecting any that
+ * does not), applies the fastest with mc_set_launch and mc_set_layout (per-
+ * lane tables as MC_LAYOUT_AUTO, the shared palette as
+ * MC_LAYOUT_PALETTE_SHARED, which then also holds for later loads) and
+ * appends it to the JSON-lines file cache_path (may be NULL).  If cache_path
+ * already holds an entry for this device and workload class, that entry is
+ * applied and nothing is timed.  Uses the GPU. */
 mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t seed,
                       const char *cache_path, mc_tuning *out);
 

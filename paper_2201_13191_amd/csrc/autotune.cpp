@@ -1,8 +1,11 @@
 // Launch-shape autotuner for the transport kernel, written against the public
 // C ABI only (plus HIP events for timing).
 //
-// Knobs: threads per block, resident blocks per compute unit and the event
-// batch.  None of them changes a photon's history, so every candidate must
+// Knobs: threads per block, resident blocks per compute unit, the event batch
+// and, for palette objects small enough for per-lane tables, the attenuation-
+// table layout (per-lane tables of every palette entry, or the shared palette
+// with per-lane tables per material).  None of them changes a photon's
+// history, so every candidate must
 // reproduce the first candidate's images bit for bit; a candidate that does
 // not is rejected (and reported), never chosen.  The winner is applied to the
 // context and, when a cache path is given, appended to a JSON-lines cache
@@ -21,7 +24,7 @@
 namespace {
 
 struct Shape {
-    int block, bpc, batch;
+    int block, bpc, batch, table;
 };
 
 std::string workload_key(mc_ctx *ctx, int nx, int ny, int nz, int n_pixels) {
@@ -36,11 +39,20 @@ std::string workload_key(mc_ctx *ctx, int nx, int ny, int nz, int n_pixels) {
     (void)mc_get_layout(ctx, &layout, &npal);
     const double vox = (double)nx * ny * nz;
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s/vox2^%d/pix2^%d/layout%d/pal%d", arch.c_str(),
+    std::snprintf(buf, sizeof buf, "%s/vox2^%d/pix2^%d/%s/pal%d", arch.c_str(),
                   (int)std::lround(std::log2(std::max(vox, 1.0))),
-                  (int)std::lround(std::log2(std::max(n_pixels, 1))), layout,
+                  (int)std::lround(std::log2(std::max(n_pixels, 1))),
+                  layout == MC_LAYOUT_GENERIC ? "generic" : "palette",
                   npal <= 8 ? 8 : (npal <= 32 ? 32 : 256));
     return buf;
+}
+
+// the table layout of a candidate as a layout request: per-lane tables are
+// what the automatic choice gives palettes of <= 32 entries; an object stored
+// with material ids and densities keeps the request it has
+mc_status apply_table(mc_ctx *ctx, int table) {
+    if (table == MC_LAYOUT_GENERIC) return MC_OK;
+    return mc_set_layout(ctx, table == MC_LAYOUT_PALETTE_LANE ? MC_LAYOUT_AUTO : table);
 }
 
 bool read_cache(const char *path, const std::string &key, Shape &s) {
@@ -53,8 +65,8 @@ bool read_cache(const char *path, const std::string &key, Shape &s) {
         char k[256];
         Shape t;
         if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"block\": %d, \"blocks_per_cu\": %d, "
-                              "\"event_batch\": %d",
-                        k, &t.block, &t.bpc, &t.batch) == 4 &&
+                              "\"event_batch\": %d, \"table_layout\": %d",
+                        k, &t.block, &t.bpc, &t.batch, &t.table) == 5 &&
             key == k) {
             s = t;          // the last entry for a key wins
             found = true;
@@ -80,9 +92,12 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
     if (read_cache(cache_path, key, cached)) {
         rc = mc_set_launch(ctx, cached.block, cached.bpc, cached.batch);
         if (rc) return rc;
+        rc = apply_table(ctx, cached.table);
+        if (rc) return rc;
         out->block = cached.block;
         out->blocks_per_cu = cached.bpc;
         out->event_batch = cached.batch;
+        out->table_layout = cached.table;
         out->from_cache = 1;
         return MC_OK;
     }
@@ -97,17 +112,28 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
         return MC_E_DEVICE;
     }
     int64_t *ref = d, *cur = d + np + ns;
+    // the table layouts open to this object: both palette forms when per-lane
+    // tables fit (<= 32 entries), else the one it has
+    int layout = 0, npal = 0;
+    rc = mc_get_layout(ctx, &layout, &npal);
+    if (rc) return rc;
+    std::vector<int> tables{layout};
+    if (layout != MC_LAYOUT_GENERIC && npal <= 32)
+        tables = {MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED};
     std::vector<Shape> cands;
-    for (int block : {64, 128, 256})
-        for (int bpc : {0, 2})
-            for (int batch : {40, 48, 52, 56, 60}) cands.push_back({block, bpc, batch});
+    for (int table : tables)
+        for (int block : {64, 128, 256})
+            for (int bpc : {0, 2})
+                for (int batch : {40, 48, 52, 56, 60}) cands.push_back({block, bpc, batch, table});
     std::vector<int64_t> h_ref(np + ns), h_cur(np + ns);
-    Shape best{0, 0, 0};
+    Shape best{0, 0, 0, layout};
     float best_ms = 1e30f;
     int rejected = 0, tried = 0;
     for (size_t i = 0; i < cands.size() && rc == MC_OK; ++i) {
         const Shape &s = cands[i];
         rc = mc_set_launch(ctx, s.block, s.bpc, s.batch);
+        if (rc) break;
+        rc = apply_table(ctx, s.table);
         if (rc) break;
         int64_t *img = i == 0 ? ref : cur;
         // one warm-up run (also the output checked), then the timed one
@@ -142,12 +168,18 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(stream);
     (void)hipFree(d);
-    if (rc) return rc;
+    if (rc) {
+        (void)apply_table(ctx, layout);
+        return rc;
+    }
     rc = mc_set_launch(ctx, best.block, best.bpc, best.batch);
+    if (rc) return rc;
+    rc = apply_table(ctx, best.table);
     if (rc) return rc;
     out->block = best.block;
     out->blocks_per_cu = best.bpc;
     out->event_batch = best.batch;
+    out->table_layout = best.table;
     out->ms = best_ms;
     out->histories_per_s = best_ms > 0.0f ? (double)n_photons / (best_ms * 1e-3) : 0.0;
     out->candidates = tried;
@@ -157,9 +189,9 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
         if (f) {
             std::fprintf(f,
                          "{\"key\": \"%s\", \"block\": %d, \"blocks_per_cu\": %d, "
-                         "\"event_batch\": %d, \"ms\": %.4f, \"photons\": %llu, "
-                         "\"candidates\": %d, \"rejected\": %d}\n",
-                         key.c_str(), best.block, best.bpc, best.batch, best_ms,
+                         "\"event_batch\": %d, \"table_layout\": %d, \"ms\": %.4f, "
+                         "\"photons\": %llu, \"candidates\": %d, \"rejected\": %d}\n",
+                         key.c_str(), best.block, best.bpc, best.batch, best.table, best_ms,
                          (unsigned long long)n_photons, tried, rejected);
             std::fclose(f);
         }

@@ -58,6 +58,7 @@ class mc_job(C.Structure):
 
 class mc_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("event_batch", C.c_int32),
+                ("table_layout", C.c_int32),
                 ("from_cache", C.c_int32), ("candidates", C.c_int32), ("rejected", C.c_int32),
                 ("ms", C.c_double), ("histories_per_s", C.c_double)]
 
