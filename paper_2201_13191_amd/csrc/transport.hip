@@ -415,7 +415,35 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     };
     int job = 0;          // batch: the lane's job
     int cur_job = 0;      // batch: the job this wave refills from
-    auto frame = [&]() __attribute__((always_inline)) -> const ProjFrame & { return BATCH ? p.jobs[job].F : p.F; };
+    // the descriptor of job j (wave-uniform j) by scalar loads
+    static_assert(sizeof(JobDesc) % 4 == 0, "descriptor copied word by word");
+    auto job_desc = [&](int j) __attribute__((always_inline)) {
+        JobDesc jd;
+        ConstWord *src = (ConstWord *)(p.jobs + j);
+        uint32_t *dst = (uint32_t *)&jd;
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(JobDesc) / 4); ++w) dst[w] = src[w];
+        return jd;
+    };
+    // with_job(active, f): f(frame, primary image, scatter image) for the
+    // active lanes, once per distinct job among them (as with_grid)
+    auto with_job = [&](bool active, auto f) __attribute__((always_inline)) {
+        if (!BATCH) {
+            if (active) f(p.F, p.prim, p.scat);
+            return;
+        }
+        unsigned long long todo = __ballot(active);
+        while (todo) {
+            const int leader = __ffsll(todo) - 1;
+            const int j = __builtin_amdgcn_readfirstlane(__shfl(job, leader));
+            const bool mine = active && job == j;
+            if (mine) {
+                const JobDesc jd = job_desc(j);
+                f(jd.F, jd.prim, jd.scat);
+            }
+            todo &= ~__ballot(mine);
+        }
+    };
 
     bool alive = false, flying = false, exhausted = false;
     PhotonStream rng;
@@ -461,7 +489,8 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         }
     };
     // a new photon: energy bin, direction in the cone, position at the source
-    auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1) __attribute__((always_inline)) {
+    auto birth = [&](uint64_t photon, uint32_t k0, uint32_t k1, const ProjFrame &F)
+        __attribute__((always_inline)) {
         pid = photon;
         rng.reset(pid, k0, k1);
         // the first block: energy bin, the cone's polar cosine and azimuth,
@@ -469,7 +498,6 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         uint32_t w[4];
         rng.draw(w);
         e = p.e_bin[pick_bin(p, w[0])];
-        const ProjFrame &F = frame();
         dir_ct = 1.0f - unit_float(w[1]) * F.omc;
         phi_w = w[2];
         ts = (double)w[3];
@@ -535,29 +563,33 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     stale = true;
                 }
             }
-        } else if (event == 2) {
-            // ---- 2. panel crossings
+        }
+        // ---- 2. panel crossings
+        with_job(event == 2, [&](const ProjFrame &F, unsigned long long *prim,
+                                 unsigned long long *scat) __attribute__((always_inline)) {
             event = 0;
             int iu, iv;
-            if (panel_hit(p, frame(), o, d, iu, iv)) {
+            if (panel_hit(p, F, o, d, iu, iv)) {
                 const float w = grid_lerp(p.eta, p.J, e);
                 const long long t = (long long)rintf(w * 1048576.0f);
-                unsigned long long *prim = BATCH ? p.jobs[job].prim : p.prim;
-                unsigned long long *scat = BATCH ? p.jobs[job].scat : p.scat;
                 if (n_int == 0) {
                     atomicAdd(prim + (size_t)iv * p.nu + iu, (unsigned long long)t);
-                    if (STATS) ++st[kStPrim];
                     end = 0;
                 } else {
                     const int su = iu / p.bu, sv = iv / p.bv;
                     atomicAdd(scat + (size_t)sv * p.snu + su, (unsigned long long)t);
-                    if (STATS) ++st[kStScat];
                     end = 1;
+                }
+                if (STATS) {
+                    // both counters, added to by value (an index chosen per lane
+                    // would put the counters in scratch memory)
+                    st[kStPrim] += n_int == 0 ? 1ull : 0ull;
+                    st[kStScat] += n_int == 0 ? 0ull : 1ull;
                 }
             } else {
                 end = 2;
             }
-        }
+        });
         if (end >= 0) {
             if (DEBUG) {
                 const uint64_t r = pid - p.first;
@@ -574,8 +606,10 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             while (dead) {
                 const unsigned nd = (unsigned)__popcll(dead);
                 const int leader = __ffsll(dead) - 1;
-                unsigned long long *ctr = BATCH ? p.job_counters + cur_job : p.counter;
-                const unsigned long long total = BATCH ? p.jobs[cur_job].n : p.n;
+                const int cj = __builtin_amdgcn_readfirstlane(cur_job);
+                const JobDesc cd = BATCH ? job_desc(cj) : JobDesc{};
+                unsigned long long *ctr = BATCH ? p.job_counters + cj : p.counter;
+                const unsigned long long total = BATCH ? cd.n : p.n;
                 unsigned long long base = 0;
                 if (lane == leader) base = atomicAdd(ctr, (unsigned long long)nd);
                 base = __shfl(base, leader);
@@ -586,11 +620,11 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                         (unsigned long long)__popcll(dead & ((1ull << lane) - 1ull));
                     if (rank < got) {
                         if (BATCH) {
-                            job = cur_job;
-                            gi = p.jobs[job].grid;
-                            birth(base + rank, p.jobs[job].key0, p.jobs[job].key1);
+                            job = cj;
+                            gi = cd.grid;
+                            birth(base + rank, cd.key0, cd.key1, cd.F);
                         } else {
-                            birth(p.first + base + rank, p.key0, p.key1);
+                            birth(p.first + base + rank, p.key0, p.key1, p.F);
                         }
                     }
                 }
@@ -609,22 +643,22 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
 
         // ---- 3b. new directions of born and scattered photons, with one
         //          azimuth evaluation for both
+        float cp = 0.0f, sp = 0.0f, stt = 0.0f;
         if (turn) {
-            turn = false;
             double sphi, cphi;
             sincos(6.283185307179586 * (double)unit_float(phi_w), &sphi, &cphi);
-            const float cp = (float)cphi, sp = (float)sphi;
-            const float ct = dir_ct;
-            const float stt = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-            if (n_int == 0) {
-                const ProjFrame &F = frame();
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    d[a] = (ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
-            } else {
-                rotate_direction(d[0], d[1], d[2], ct, stt, cp, sp);
-            }
+            cp = (float)cphi;
+            sp = (float)sphi;
+            stt = sqrtf(fmaxf(0.0f, 1.0f - dir_ct * dir_ct));
+            if (n_int != 0) rotate_direction(d[0], d[1], d[2], dir_ct, stt, cp, sp);
         }
+        with_job(turn && n_int == 0, [&](const ProjFrame &F, unsigned long long *,
+                                         unsigned long long *) __attribute__((always_inline)) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                d[a] = (dir_ct * F.ax[a] + (stt * cp) * F.eu[a]) + (stt * sp) * F.ev[a];
+        });
+        turn = false;
 
         // ---- 4. start flights (new photons and scattered ones); the LDS tables
         //         are rebuilt first if the energy changed since the last flight
