@@ -307,6 +307,14 @@ constexpr uint32_t kMinSkip = 4;             // shortest run taken at once
 constexpr int kPrefetch = MCX_PREFETCH;   // march steps whose voxel loads are issued together
 constexpr int kLdsHeader = 256 + 64;   // floats: palette densities, then 256 palette ids
 
+// the value lane `src` (wave-uniform) holds, read into a scalar register
+// without a trip through LDS
+__device__ __forceinline__ unsigned long long lane_value(unsigned long long v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -400,7 +408,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         unsigned long long todo = __ballot(active);
         while (todo) {
             const int leader = __ffsll(todo) - 1;
-            const int g = __builtin_amdgcn_readfirstlane(__shfl(gi, leader));
+            const int g = __builtin_amdgcn_readlane(gi, leader);
             const bool mine = active && gi == g;
             if (mine) {
                 VoxelGrid gs;
@@ -435,7 +443,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         unsigned long long todo = __ballot(active);
         while (todo) {
             const int leader = __ffsll(todo) - 1;
-            const int j = __builtin_amdgcn_readfirstlane(__shfl(job, leader));
+            const int j = __builtin_amdgcn_readlane(job, leader);
             const bool mine = active && job == j;
             if (mine) {
                 const JobDesc jd = job_desc(j);
@@ -612,7 +620,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 const unsigned long long total = BATCH ? cd.n : p.n;
                 unsigned long long base = 0;
                 if (lane == leader) base = atomicAdd(ctr, (unsigned long long)nd);
-                base = __shfl(base, leader);
+                base = lane_value(base, leader);
                 const unsigned long long got =
                     base < total ? (total - base < nd ? total - base : nd) : 0ull;
                 if (!alive) {
@@ -930,7 +938,7 @@ __global__ void __launch_bounds__(256) march_probe_kernel(const KParams p,
             const int leader = __ffsll(dead) - 1;
             unsigned long long base = 0;
             if (lane == leader) base = atomicAdd(p.counter, (unsigned long long)nd);
-            base = __shfl(base, leader);
+            base = lane_value(base, leader);
             const unsigned long long got =
                 base < p.n ? (p.n - base < nd ? p.n - base : nd) : 0ull;
             if (got < nd) exhausted = true;
