@@ -271,6 +271,27 @@ def main():
         log(f"march probe {best[0]:.4g} steps/s (refill {best[1]}), transport "
             f"{t_rate:.4g} voxel lookups/s = {t_rate / best[0]:.1%}")
 
+    # tally probe: int64 atomic adds alone, spread over an image of the primary's size
+    tally = None
+    if not args.no_probe:
+        log("tally probe")
+        n_pix = geo["nu"] * geo["nv"]
+        n_adds = 200_000_000
+        img = torch.zeros(n_pix, dtype=torch.int64, device=dev)
+        mcx.mc_atomic_probe_async(g.ctx, n_adds, 1, img, n_pix, stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            mcx.mc_atomic_probe_async(g.ctx, n_adds, 1, img, n_pix, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        rate = 3 * n_adds / (a.elapsed_time(b) * 1e-3)
+        t_adds = (st["primary_hits"] + st["scatter_hits"]) / launch_s
+        tally = {"adds_per_s": rate, "pixels": n_pix, "transport_adds_per_s": t_adds,
+                 "frac": t_adds / rate}
+        log(f"tally probe {rate:.4g} int64 adds/s, transport {t_adds:.4g} = {t_adds / rate:.2%}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -319,6 +340,7 @@ def main():
                        "bytes_per_step": gather_bytes, "achieved_GBs": gather_gbs,
                        "hbm_peak_GBs": HBM_PEAK_GBS, "frac": gather_gbs / HBM_PEAK_GBS},
             "march_probe": probe,
+            "tally_probe": tally,
         },
         "cpu_baseline": cpu,
     }

@@ -204,6 +204,18 @@ mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t 
 mc_status mc_march_probe_async(mc_ctx *ctx, float angle_rad, uint64_t n_rays, uint64_t seed,
                                int refill_batch, uint64_t *d_sum, void *stream);
 
+/* Tally probe (a measuring instrument, not part of the method): n_adds int64
+ * atomic additions of 1 to d_image[n_pixels] (device int64, not cleared;
+ * 1 <= n_pixels < 2^32).  Add i goes to pixel floor(h * n_pixels / 2^32),
+ * h = H(lo32(i) ^ s ^ hi32(i) * 0x9E3779B9) with s = lo32(seed) ^ hi32(seed)
+ * and H the 32-bit integer hash x ^= x >> 16; x *= 0x7feb352d; x ^= x >> 15;
+ * x *= 0x846ca68b; x ^= x >> 16 (arithmetic mod 2^32), i.e. spread uniformly
+ * over the image like the transport's tallies (the primary and scatter
+ * images of eqs. 6-7) over a panel.  Stream-ordered; its add rate is the
+ * ceiling of the transport's tally atomics on an image of that size. */
+mc_status mc_atomic_probe_async(mc_ctx *ctx, uint64_t n_adds, uint64_t seed, int64_t *d_image,
+                                uint64_t n_pixels, void *stream);
+
 /* Uniform-cell map of a voxel object, as the march uses it to take runs of
  * identical voxels at once (host only, no context): codes[nz][ny][nx] are
  * per-voxel codes (the palette index of each (material, density) pair);

@@ -22,6 +22,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contr
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
+           ("probes.hip", "hip"),
            ("runtime.hip", "hip"),
            ("tables.cpp", "cxx"), ("cells.cpp", "cxx"), ("autotune.cpp", "hiphost")]
 

@@ -25,6 +25,8 @@ namespace mcx {
 hipError_t launch_march_probe(const KParams &p, int layout, int grid, int block,
                               unsigned long long *sum, hipStream_t stream);
 int march_probe_blocks_per_cu(int layout, int block);
+hipError_t launch_atomic_probe(unsigned long long *img, uint32_t n_pix, unsigned long long n,
+                               uint32_t seed, int grid, hipStream_t stream);
 hipError_t launch_transport(const KParams &p, int layout, int grid, int block, bool stats,
                             bool debug, hipStream_t stream);
 hipError_t launch_sample(const KParams &p, int process, int material, float e_kev, uint64_t n,
@@ -817,6 +819,24 @@ mc_status mc_march_probe_async(mc_ctx *c, float beta, uint64_t n_rays, uint64_t 
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, need));
     hipError_t e = launch_march_probe(p, p.G.layout, grid, block, (unsigned long long *)d_sum, s);
     if (e != hipSuccess) return hip_fail(c, e, "march probe launch");
+    return MC_OK;
+}
+
+mc_status mc_atomic_probe_async(mc_ctx *c, uint64_t n_adds, uint64_t seed, int64_t *d_image,
+                                uint64_t n_pixels, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_image) return fail(c, MC_E_INVALID_ARG, "null image");
+    if (n_pixels < 1 || n_pixels > 0xFFFFFFFFull)
+        return fail(c, MC_E_INVALID_ARG, "n_pixels must be 1 .. 2^32 - 1");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    if (n_adds == 0) return MC_OK;
+    const uint64_t need = (n_adds + 255) / 256;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)8 * c->n_cu, need));
+    hipError_t e = launch_atomic_probe((unsigned long long *)d_image, (uint32_t)n_pixels, n_adds,
+                                       (uint32_t)seed ^ (uint32_t)(seed >> 32), grid,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "atomic probe launch");
     return MC_OK;
 }
 

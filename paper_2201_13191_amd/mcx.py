@@ -32,7 +32,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
-           "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async"]
+           "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -108,6 +108,7 @@ def load():
         "mc_project_async": ([P, F, U64, U64, P, P, P], I),
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
         "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
+        "mc_atomic_probe_async": ([P, U64, U64, P, U64, P], I),
         "mc_cell_map": ([P, I, I, I, P], I),
         "mc_flip2d_async": ([P, P, P, I, I, I, I, F, F, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
@@ -263,6 +264,11 @@ def mc_cell_map(codes):
     if rc:
         raise MCXError(rc, "bad cell-map arguments")
     return out
+
+
+def mc_atomic_probe_async(ctx, n_adds, seed, d_image, n_pixels, stream=None):
+    _check(ctx, load().mc_atomic_probe_async(ctx, n_adds, seed, _dev(d_image), n_pixels,
+                                             _stream(stream)))
 
 
 def mc_march_probe_async(ctx, angle, n_rays, seed, refill_batch, d_sum, stream=None):

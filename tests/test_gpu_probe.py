@@ -76,3 +76,38 @@ def test_probe_layouts_and_errors(torch_gpu):
         with pytest.raises(mcx.MCXError):
             mcx.mc_march_probe_async(g.ctx, 0.4, 10, 3, 8, None)
     assert out[0] == out[1] and out[0][1] > 0
+
+
+def _probe_pixels(n, seed, n_pix):
+    """Pixel of each add of the tally probe, written from its definition in
+    the header (32-bit arithmetic in uint64 with explicit wrap)."""
+    m = (1 << 32) - 1
+    i = np.arange(n, dtype=np.uint64)
+    s = np.uint64((seed ^ (seed >> 32)) & m)
+    x = ((i & np.uint64(m)) ^ s ^ (((i >> np.uint64(32)) * np.uint64(0x9E3779B9)) & np.uint64(m)))
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x7feb352d)) & np.uint64(m)
+    x ^= x >> np.uint64(15)
+    x = (x * np.uint64(0x846ca68b)) & np.uint64(m)
+    x ^= x >> np.uint64(16)
+    return ((x * np.uint64(n_pix)) >> np.uint64(32)).astype(np.int64)
+
+
+@pytest.mark.parametrize("n,n_pix", [(1, 1), (1_000_003, 4099), (3_000_000, 512 * 512)])
+def test_atomic_probe_histogram(torch_gpu, n, n_pix):
+    """Every add lands on the pixel the definition gives: the image equals the
+    host histogram, also when added onto a non-zero image."""
+    torch = torch_gpu
+    say("atomic probe", n, n_pix)
+    ctx = mcx.mc_create(0)
+    try:
+        seed = 0x1234_5678_9ABC
+        img = torch.full((n_pix,), 7, dtype=torch.int64, device="cuda")
+        mcx.mc_atomic_probe_async(ctx, n, seed, img, n_pix)
+        torch.cuda.synchronize()
+        ref = np.bincount(_probe_pixels(n, seed, n_pix), minlength=n_pix) + 7
+        assert np.array_equal(img.cpu().numpy(), ref)
+        with pytest.raises(mcx.MCXError):
+            mcx.mc_atomic_probe_async(ctx, n, seed, img, 0)
+    finally:
+        mcx.mc_destroy(ctx)
