@@ -240,6 +240,16 @@ def main():
     log(f"{n * args.steps / wall:.4g} histories/s, {launch_s * 1e3:.2f} ms per step (events), "
         f"steps/history {st['steps'] / max(st['histories'], 1):.1f}")
 
+    # end to end through the blocking entry point: host images (clear, launch,
+    # copy back over PCIe); reported beside the value, never as it
+    pg, sg = g.images()
+    mcx.mc_project(g.ctx, w["angle"], n, w["seed"], pg, sg)
+    t_e = time.perf_counter()
+    for _ in range(2):
+        mcx.mc_project(g.ctx, w["angle"], n, w["seed"], pg, sg)
+    end_to_end_ms = (time.perf_counter() - t_e) / 2 * 1e3
+    log(f"mc_project with host images: {end_to_end_ms:.2f} ms")
+
     # march probe: the fixed-step march of straight rays alone (no physics)
     probe = None
     if not args.no_probe:
@@ -343,6 +353,8 @@ def main():
             "tally_probe": tally,
         },
         "cpu_baseline": cpu,
+        "end_to_end": {"entry": "mc_project (host images)", "ms": end_to_end_ms,
+                       "histories_per_s": n / (end_to_end_ms * 1e-3)},
     }
     print(json.dumps(out), flush=True)
     g.close()
