@@ -409,15 +409,15 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         while (todo) {
             const int leader = __ffsll(todo) - 1;
             const int g = __builtin_amdgcn_readlane(gi, leader);
-            const bool mine = active && gi == g;
-            if (mine) {
-                VoxelGrid gs;
-                ConstWord *src = (ConstWord *)(p.grids + g);
-                uint32_t *dst = (uint32_t *)&gs;
+            // read in control flow uniform across the wave (inside the
+            // divergent branch below it would become vector loads)
+            VoxelGrid gs;
+            ConstWord *src = (ConstWord *)(p.grids + g);
+            uint32_t *dst = (uint32_t *)&gs;
 #pragma unroll
-                for (int w = 0; w < (int)(sizeof(VoxelGrid) / 4); ++w) dst[w] = src[w];
-                f(gs);
-            }
+            for (int w = 0; w < (int)(sizeof(VoxelGrid) / 4); ++w) dst[w] = src[w];
+            const bool mine = active && gi == g;
+            if (mine) f(gs);
             todo &= ~__ballot(mine);
         }
     };
@@ -444,11 +444,9 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         while (todo) {
             const int leader = __ffsll(todo) - 1;
             const int j = __builtin_amdgcn_readlane(job, leader);
+            const JobDesc jd = job_desc(j);      // uniform control flow: scalar loads
             const bool mine = active && job == j;
-            if (mine) {
-                const JobDesc jd = job_desc(j);
-                f(jd.F, jd.prim, jd.scat);
-            }
+            if (mine) f(jd.F, jd.prim, jd.scat);
             todo &= ~__ballot(mine);
         }
     };
