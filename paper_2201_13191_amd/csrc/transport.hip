@@ -359,12 +359,25 @@ __device__ __forceinline__ uint32_t saturated_index(float c) {
     return i;
 }
 
+// A pointer taken from a descriptor copied out of memory (a batch's object or
+// job table) is a generic pointer to the compiler, which then issues flat
+// accesses; these always address device memory, and saying so gives global
+// ones (with a scalar base when the pointer is uniform).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *dev(const T *q) {
+    return (const __attribute__((address_space(1))) T *)q;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *dev_rw(T *q) {
+    return (__attribute__((address_space(1))) T *)q;
+}
+
 // uniform-cell word of the cell holding the (clamped) voxel of centre q
 __device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[3]) {
     const uint32_t cx = voxel_index(q[0], g.cmax[0]) >> kCellLog;
     const uint32_t cy = voxel_index(q[1], g.cmax[1]) >> kCellLog;
     const uint32_t cz = voxel_index(q[2], g.cmax[2]) >> kCellLog;
-    return g.cells[__umul24(__umul24(cz, (uint32_t)g.ncy) + cy, (uint32_t)g.ncx) + cx];
+    return dev(g.cells)[__umul24(__umul24(cz, (uint32_t)g.ncy) + cy, (uint32_t)g.ncx) + cx];
 }
 
 // MODE: layout of the single object (ignored for batches, where each lane
@@ -579,11 +592,15 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 const float w = grid_lerp(p.eta, p.J, e);
                 const long long t = (long long)rintf(w * 1048576.0f);
                 if (n_int == 0) {
-                    atomicAdd(prim + (size_t)iv * p.nu + iu, (unsigned long long)t);
+                    __hip_atomic_fetch_add(dev_rw(prim) + (size_t)iv * p.nu + iu,
+                                           (unsigned long long)t, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                     end = 0;
                 } else {
                     const int su = iu / p.bu, sv = iv / p.bv;
-                    atomicAdd(scat + (size_t)sv * p.snu + su, (unsigned long long)t);
+                    __hip_atomic_fetch_add(dev_rw(scat) + (size_t)sv * p.snu + su,
+                                           (unsigned long long)t, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                     end = 1;
                 }
                 if (STATS) {
@@ -729,7 +746,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 if (lay == kGeneric)
                     mat = (int)c;
                 else
-                    mat = BATCH ? (int)gl.pal_id[c] : (int)s_pal_id[c];
+                    mat = BATCH ? (int)dev(gl.pal_id)[c] : (int)s_pal_id[c];
                 event = 1;
                 flying = false;
             };
@@ -816,9 +833,9 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     const uint32_t off = brick_offset(gl, index(q[0], gl.cmax[0]),
                                                       index(q[1], gl.cmax[1]),
                                                       index(q[2], gl.cmax[2]));
-                    code[u] = gl.vox[off];
+                    code[u] = dev(gl.vox)[off];
                     vr[u] = 0.0f;
-                    if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = gl.vrho[off];
+                    if (BATCH ? gl.layout == kGeneric : MODE == kGeneric) vr[u] = dev(gl.vrho)[off];
                     if (u % 4 != 3) {
 #pragma unroll
                         for (int a = 0; a < 3; ++a) q[a] = q[a] + G[a];
@@ -872,8 +889,8 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     float rho = vr[u];
                     uint32_t id = code[u];
                     if (lay == kPaletteShared) {
-                        rho = BATCH ? gl.pal_rho[code[u]] : s_pal_rho[code[u]];
-                        id = BATCH ? gl.pal_id[code[u]] : s_pal_id[code[u]];
+                        rho = BATCH ? dev(gl.pal_rho)[code[u]] : s_pal_rho[code[u]];
+                        id = BATCH ? dev(gl.pal_id)[code[u]] : s_pal_id[code[u]];
                     }
                     const float mu = rho * mm[id * bs];
                     return __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
