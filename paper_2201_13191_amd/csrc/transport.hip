@@ -727,11 +727,14 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         //         that reaches tau* is recorded, and the interaction point or the
         //         exit follows the group.
         static_assert(kPrefetch % 4 == 0, "groups hold whole anchor periods");
+        // march(each_object): the loop of groups; each_object(f) runs one
+        // group f for the flying lanes with their object's descriptor
+        auto march = [&](auto each_object) __attribute__((always_inline)) {
         for (;;) {
             if (!__any(flying)) break;
             if (__popcll(__ballot(alive && !flying)) >= (unsigned)p.event_batch) break;
             if (!flying) continue;
-            with_grid(true, [&](const VoxelGrid &gl) __attribute__((always_inline)) {
+            each_object([&](const VoxelGrid &gl) __attribute__((always_inline)) {
             const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
             const bool skips = lane_pal && gl.cells != nullptr;
             const int lay = BATCH ? gl.layout : MODE;
@@ -918,6 +921,27 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                 }
             }
             });
+        }
+        };
+        if (!BATCH) {
+            march([&](auto f) __attribute__((always_inline)) { f(p.G); });
+        } else {
+            // no flight starts while marching: when every flying lane is on one
+            // object, its descriptor is read once for the whole march
+            const unsigned long long fl = __ballot(flying);
+            const int g0 = fl ? __builtin_amdgcn_readlane(gi, __ffsll(fl) - 1) : 0;
+            if (fl != 0ull && __ballot(flying && gi != g0) == 0ull) {
+                VoxelGrid g;
+                ConstWord *src = (ConstWord *)(p.grids + g0);
+                uint32_t *dst = (uint32_t *)&g;
+#pragma unroll
+                for (int w = 0; w < (int)(sizeof(VoxelGrid) / 4); ++w) dst[w] = src[w];
+                march([&](auto f) __attribute__((always_inline)) {
+                    if (flying) f(g);
+                });
+            } else {
+                march([&](auto f) __attribute__((always_inline)) { with_grid(true, f); });
+            }
         }
     }
     if (STATS) {
