@@ -124,7 +124,7 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
     for (int table : tables)
         for (int block : {64, 128, 256})
             for (int bpc : {0, 2})
-                for (int batch : {40, 48, 52, 56, 60}) cands.push_back({block, bpc, batch, table});
+                for (int batch : {48, 52, 56, 58, 60}) cands.push_back({block, bpc, batch, table});
     std::vector<int64_t> h_ref(np + ns), h_cur(np + ns);
     Shape best{0, 0, 0, layout};
     float best_ms = 1e30f;

@@ -70,7 +70,7 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 56;
+constexpr int kDefaultEventBatch = 58;
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or
