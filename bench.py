@@ -9,7 +9,7 @@ GPU memory before the timed region.  A "step" is one whole projection:
 clearing both images and the transport kernel over all photons.
 
 Output: one JSON line (metric, value, roofline of the transport kernel, CPU
-oracle baseline).  `python bench.py --gpus N` with N > 1 exits: this build
+oracle baseline).  `python bench.py --gpus N` with N > 1 exits: the benchmark
 measures one GPU.
 """
 import argparse
@@ -166,9 +166,9 @@ def main():
                          "to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(projections and photon ranges shard without communication; see DESIGN.md)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (projections "
+              "and photon-id ranges would shard across GPUs without communication, the images "
+              "summed once at the end)", file=sys.stderr)
         sys.exit(2)
 
     import torch

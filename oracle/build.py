@@ -1,6 +1,6 @@
 """Build the CPU oracle (liboracle_mco.so) with plain gcc.
 
-Test infrastructure: the oracle is the judge of the GPU library.  Flags keep
+Test infrastructure: the oracle is the reference for the GPU library.  Flags keep
 IEEE semantics: no fused multiply-add contraction, no fast-math, SSE2 floating
 point (x86-64 default), so every fp32/fp64 operation rounds exactly once.
 """

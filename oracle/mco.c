@@ -2,7 +2,7 @@
  * mco.c -- sequential CPU oracle of the analog Monte Carlo photon-transport
  * forward projection of arXiv 2201.13191 (section II-A).
  *
- * TEST INFRASTRUCTURE ONLY: the judge of the GPU library, never part of the
+ * TEST INFRASTRUCTURE ONLY: the reference for the GPU library, never part of the
  * product path.  Written independently of the GPU library; see mco.h for the
  * scope.  Every operation that can round is spelled out in the order the
  * transport specification fixes, so that one seed has exactly one result:

@@ -4,7 +4,7 @@
  * Correction for High-Resolution Flat-Panel CT Based on a Fast Monte Carlo
  * Photon Transport Model", arXiv 2201.13191).
  *
- * TEST INFRASTRUCTURE ONLY.  This library is the judge the GPU library is
+ * TEST INFRASTRUCTURE ONLY.  This library is the reference the GPU library is
  * compared against.  Only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it; the product path never does.  It shares
  * no code, header, table generator or constant generator with the GPU

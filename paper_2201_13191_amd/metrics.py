@@ -1,4 +1,4 @@
-"""Image metrics used to judge scatter estimates (host-side evaluation).
+"""Image metrics used to score scatter estimates (host-side evaluation).
 
 * rel_l2(a, b) = ||a - b|| / ||b|| over the image (b is the reference).
 * debiased_rel_rms(a, batches): the reference b is the mean of B independent
