@@ -270,7 +270,8 @@ mc_status mc_get_layout(mc_ctx *ctx, int *layout, int *palette_size);
 /* Launch shape of the transport kernel (0 = automatic): threads per block
  * (64, 128, 192 or 256), resident blocks per compute unit, and the event
  * batch: how many of a wave's 64 lanes must be waiting for an interaction or
- * a panel crossing before the wave stops marching and handles them (1 .. 64).
+ * a panel crossing before the wave stops marching and handles them (1 .. 64;
+ * automatic: 58 for single projections, 54 for mc_project_batch).
  * Results never depend on these. */
 mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int event_batch);
 

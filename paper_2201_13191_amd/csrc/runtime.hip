@@ -70,7 +70,8 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 58;
+constexpr int kDefaultEventBatch = 58;        // single projections (swept 54..62)
+constexpr int kDefaultBatchEventBatch = 54;   // batched launches (swept 48..60)
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or
@@ -937,6 +938,7 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
     p.job_counters = (unsigned long long *)(db + gb + jbytes);
     p.n_jobs = n_jobs;
     p.F = hj[0].F;
+    if (c->event_batch <= 0) p.event_batch = kDefaultBatchEventBatch;
     const bool stats = c->stats_on;
     if (!stats) p.stats = nullptr;
     const int block = c->block > 0 ? c->block : 256;
