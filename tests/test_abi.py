@@ -93,6 +93,12 @@ def test_host_context_validation(host_ctx):
         mcx.mc_get_tables(ctx, 5)                                    # no spectrum yet
     assert e.value.code == mcx.MC_E_STATE
     assert mcx.load().mc_create(None, 0) == mcx.MC_E_INVALID_ARG
+    # tally probe: arguments are checked before any device is touched
+    L, fake = mcx.load(), C.c_void_p(256)
+    assert L.mc_atomic_probe_async(ctx, 10, 1, None, 100, None) == mcx.MC_E_INVALID_ARG
+    assert L.mc_atomic_probe_async(ctx, 10, 1, fake, 0, None) == mcx.MC_E_INVALID_ARG
+    assert L.mc_atomic_probe_async(ctx, 10, 1, fake, 1 << 32, None) == mcx.MC_E_INVALID_ARG
+    assert L.mc_atomic_probe_async(ctx, 10, 1, fake, 100, None) == mcx.MC_E_STATE   # no device
 
 
 @pytest.mark.parametrize("spec", ["mono60", "kramers150", "mono1000", "mono1.5"])
