@@ -135,6 +135,20 @@ mc_status mc_set_geometry(mc_ctx *ctx, const mc_geometry *g);
  * energy is the energy of a bin drawn with probability w_k / sum(w). */
 mc_status mc_set_spectrum(mc_ctx *ctx, const float *e_keV, const float *w, int n_bins);
 
+/* A bremsstrahlung spectrum for mc_set_spectrum (host only, no context): bins
+ * [lo, lo + bin_keV) for lo = 1, 1 + bin_keV, ... < kvp, with centres
+ * lo + bin_keV/2 in out_e and Kramers' weights (kvp - E)/E attenuated by al_mm
+ * of aluminium in out_w (0 for a centre at or above kvp).  The aluminium
+ * attenuation is a two-term fit, mu/rho = 26583/E^3 + 0.1434 cm^2/g at 2.699
+ * g/cm^3: it shapes a synthetic input, it is not a cross-section table of the
+ * transport (the paper's spectrum is simulated from its X-ray tube, section
+ * II-D-1; this helper stands in for it with a textbook shape).
+ * *n_bins receives the number of bins; with out_e and out_w both NULL only
+ * that is computed, else both must hold capacity >= *n_bins floats.
+ * 1 < kvp <= 1000, al_mm >= 0, bin_keV > 0. */
+mc_status mc_make_kramers(double kvp, double al_mm, double bin_keV, float *out_e, float *out_w,
+                          int capacity, int *n_bins);
+
 /* Detector energy response eta(E) (eq. (3)/(7)) on the 1 keV grid
  * E_j = 1 + j keV, n >= 1 values (the last one repeats beyond n).  Default
  * eta(E) = E (energy integrating).  eta = 1 counts photons. */

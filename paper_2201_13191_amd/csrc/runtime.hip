@@ -1197,6 +1197,28 @@ mc_status mc_flip2d_async(mc_ctx *c, const float *d_in, float *d_out, int nx, in
     return e == hipSuccess ? MC_OK : hip_fail(c, e, "flip");
 }
 
+mc_status mc_make_kramers(double kvp, double al_mm, double bin_keV, float *out_e, float *out_w,
+                          int capacity, int *n_bins) {
+    if (!n_bins || !(kvp > 1.0) || !(kvp <= 1000.0) || !(bin_keV > 0.0) || !(al_mm >= 0.0) ||
+        !std::isfinite(al_mm) || !((kvp - 1.0) / bin_keV <= 1e6))
+        return MC_E_INVALID_ARG;
+    // bins [lo, lo + bin) from lo = 1 keV while lo < kVp, centres lo + bin/2
+    const int n = (int)std::ceil((kvp - 1.0) / bin_keV);
+    *n_bins = n;
+    if (!out_e && !out_w) return MC_OK;          // size query
+    if (!out_e || !out_w || capacity < n) return MC_E_INVALID_ARG;
+    for (int i = 0; i < n; ++i) {
+        const double e = (1.0 + (double)i * bin_keV) + 0.5 * bin_keV;
+        // Kramers' (kVp - E)/E behind al_mm of aluminium (rho 2.699 g/cm^3,
+        // mu/rho ~ 26583/E^3 + 0.1434 cm^2/g: a fit that only shapes an input)
+        const double mu_rho = 26583.0 / (e * e * e) + 0.1434;
+        const double w = (kvp - e) / e * std::exp(-mu_rho * 2.699 * (al_mm / 10.0));
+        out_e[i] = (float)e;
+        out_w[i] = e < kvp ? (float)w : 0.0f;
+    }
+    return MC_OK;
+}
+
 mc_status mc_savgol_weights(int window, int order, float *weights) {
     if (!weights || window < 1 || window > 31 || window % 2 == 0 || order < 0 || order >= window)
         return MC_E_INVALID_ARG;

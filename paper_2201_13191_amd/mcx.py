@@ -32,7 +32,8 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_conv3x3_wgrad_async", "mc_nn_bias_grad_async", "mc_nn_flip_weights_async",
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
-           "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async"]
+           "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
+           "mc_make_kramers"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -109,6 +110,7 @@ def load():
         "mc_project_range_async": ([P, F, U64, U64, U64, P, P, P], I),
         "mc_march_probe_async": ([P, F, U64, U64, I, P, P], I),
         "mc_atomic_probe_async": ([P, U64, U64, P, U64, P], I),
+        "mc_make_kramers": ([C.c_double, C.c_double, C.c_double, P, P, I, C.POINTER(C.c_int)], I),
         "mc_cell_map": ([P, I, I, I, P], I),
         "mc_flip2d_async": ([P, P, P, I, I, I, I, F, F, P], I),
         "mc_debug_histories": ([P, F, U64, U64, U64, P, P, P, P], I),
@@ -364,6 +366,19 @@ def mc_upsample_cubic_async(ctx, d_in, d_out, nx, ny, factor, stream=None):
 def mc_flip2d_async(ctx, d_in, d_out, nx, ny, flip_x, flip_y, alpha=1.0, beta=0.0, stream=None):
     _check(ctx, load().mc_flip2d_async(ctx, _dev(d_in), _dev(d_out), nx, ny, int(flip_x),
                                        int(flip_y), float(alpha), float(beta), _stream(stream)))
+
+
+def mc_make_kramers(kvp, al_mm=0.0, bin_kev=1.0):
+    """(bin centres, weights) as float32 arrays; see include/mcx.h."""
+    n = C.c_int(0)
+    rc = load().mc_make_kramers(kvp, al_mm, bin_kev, None, None, 0, C.byref(n))
+    if rc:
+        raise MCXError(rc, "bad spectrum parameters")
+    e, w = np.zeros(n.value, np.float32), np.zeros(n.value, np.float32)
+    rc = load().mc_make_kramers(kvp, al_mm, bin_kev, _np(e), _np(w), n.value, C.byref(n))
+    if rc:
+        raise MCXError(rc, "bad spectrum parameters")
+    return e, w
 
 
 def mc_savgol_weights(window, order):

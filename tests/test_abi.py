@@ -185,3 +185,27 @@ def test_cell_map_matches_brute_force(lib, shape, seed):
     assert np.array_equal(got, brute_cell_map(codes))
     uniform = mcx.mc_cell_map(np.full((16, 24, 8), 7, np.uint8))
     assert np.all(uniform == (7 | (255 << 8)))
+
+
+@pytest.mark.parametrize("kvp,al,bin_kev", [(150, 2.0, 1.0), (90, 1.0, 1.0), (60, 0.0, 2.5),
+                                             (1000, 5.0, 7.0)])
+def test_make_kramers_matches_input_recipe(lib, kvp, al, bin_kev):
+    """The C helper gives the synthetic inputs' Kramers spectrum (same bins; the
+    weights to fp32 rounding of the same fp64 expression)."""
+    e, w = mcx.mc_make_kramers(kvp, al, bin_kev)
+    er, wr = inputs.kramers_spectrum(kvp, al, bin_kev)
+    assert e.shape == er.shape and np.array_equal(e, er)
+    assert np.allclose(w, wr, rtol=2e-7, atol=0.0)
+    assert (w >= 0.0).all() and w.max() > 0.0
+
+
+def test_make_kramers_arguments(lib):
+    L, n = mcx.load(), C.c_int(0)
+    for args in [(1.0, 0.0, 1.0), (150.0, -1.0, 1.0), (150.0, 0.0, 0.0), (1001.0, 0.0, 1.0)]:
+        assert L.mc_make_kramers(*args, None, None, 0, C.byref(n)) == mcx.MC_E_INVALID_ARG
+    assert L.mc_make_kramers(150.0, 0.0, 1.0, None, None, 0, None) == mcx.MC_E_INVALID_ARG
+    assert L.mc_make_kramers(150.0, 0.0, 1.0, None, None, 0, C.byref(n)) == mcx.MC_OK
+    assert n.value == 149
+    small = np.zeros(10, np.float32)
+    assert L.mc_make_kramers(150.0, 0.0, 1.0, small.ctypes.data_as(C.c_void_p),
+                             small.ctypes.data_as(C.c_void_p), 10, C.byref(n)) == mcx.MC_E_INVALID_ARG
