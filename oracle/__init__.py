@@ -19,6 +19,7 @@ NO_SCATTER = 1
 PROC_SOURCE_ENERGY, PROC_RAYLEIGH, PROC_COMPTON, PROC_SOURCE_DIR = 0, 1, 2, 3
 END_PRIMARY, END_SCATTER, END_MISSED, END_PHOTO, END_CUTOFF, END_CAP = range(6)
 FIRST_NONE, FIRST_PHOTO, FIRST_RAYLEIGH, FIRST_COMPTON = range(4)
+READING_GRID, READING_PLAIN = 0, 1
 
 
 class Material(C.Structure):
@@ -67,6 +68,11 @@ def lib():
         L.mco_project_mt.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, P, P, C.c_int]
         L.mco_debug_histories.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, C.c_uint64,
                                           P, P, P, P]
+        L.mco_debug_paths.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, C.c_uint64,
+                                      P, P, P]
+        L.mco_set_reading.argtypes = [P, C.c_int]
+        L.mco_test_rotate.argtypes = [P, C.c_float, C.c_double, P]
+        L.mco_test_rotate.restype = None
         L.mco_test_sample.argtypes = [P, C.c_int, C.c_int, C.c_float, C.c_uint64,
                                       C.c_uint64, P, P]
         L.mco_detector_pixel.argtypes = [P, C.c_float, P, P, C.POINTER(C.c_int),
@@ -185,6 +191,19 @@ class Oracle:
                                                 _ptr(steps), _ptr(end), _ptr(first_t)))
         return n_int, steps, end, first_t
 
+    def debug_paths(self, angle, first, m, seed):
+        """(first interaction point [m,3] (NaN if none), crossed pixel iv*nu+iu
+        (-1 if none), energy at the end of the history) per history."""
+        x1 = np.zeros((m, 3), np.float32)
+        pix = np.zeros(m, np.int32)
+        e_end = np.zeros(m, np.float32)
+        self._check(self._L.mco_debug_paths(self._h, angle, first, m, seed, _ptr(x1),
+                                            _ptr(pix), _ptr(e_end)))
+        return x1, pix, e_end
+
+    def set_reading(self, reading):
+        self._check(self._L.mco_set_reading(self._h, reading))
+
     def test_sample(self, process, material, e_kev, n, seed):
         cos = np.zeros(n, np.float32)
         e = np.zeros(n, np.float32)
@@ -240,6 +259,14 @@ def uniform(x):
     x = np.ascontiguousarray(x, dtype=np.uint32)
     out = np.zeros(x.shape, np.float32)
     lib().mco_uniform_batch(_ptr(x), x.size, _ptr(out))
+    return out
+
+
+def rotate(d, cos_theta, phi):
+    """The transport's direction update after one scattering."""
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    out = np.zeros(3, np.float32)
+    lib().mco_test_rotate(_ptr(d), float(cos_theta), float(phi), _ptr(out))
     return out
 
 

@@ -74,6 +74,7 @@ struct mco_ctx {
     int J;
     float *t_pe, *t_coh, *t_inc, *t_eta;
     int tables_dirty;
+    int reading;                /* MCO_READING_GRID or MCO_READING_PLAIN */
     mco_stats stats;
 };
 
@@ -585,6 +586,9 @@ typedef struct {
     uint16_t n_int;
     uint32_t steps;
     uint8_t end, first;
+    float x1[3];      /* first interaction point (NaN when none)          */
+    int32_t pix;      /* crossed pixel iv * nu + iu on the panel, or -1    */
+    float e_end;      /* energy when the history ended                      */
 } hist_t;
 
 /* Optical-depth increments are kept on the grid of 2^-32 (and below 2^21),
@@ -651,6 +655,49 @@ static int march(const mco_ctx *c, const proj_t *P, const float p[3], const floa
     }
 }
 
+/* The plain reading of the fixed-step march (section II-C-2 fixes only that
+ * the step is a free parameter): from the box entry, steps of length
+ * step_mm, the last one clipped at the exit; each step looks up the voxel
+ * holding its true midpoint, p + d (t_in + t + len/2), and adds mu * len to
+ * the optical depth; the photon interacts in the first step where the depth
+ * reaches tau_star, at the distance (tau_star - tau) / mu into that step.
+ * Positions, lengths and the depth are fp64 throughout; the interaction
+ * point is rounded to fp32 once.  Written independently of march(): it
+ * shares no step bookkeeping with it and is used only to show that the
+ * rounding-exact reading above stays within the parity tolerances of this
+ * one (selected by mco_set_reading). */
+static int march_plain(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
+                       float tin, float tout, const float *mm, double tau_star, float pint[3],
+                       size_t *vox, uint32_t *steps) {
+    const double dl = (double)c->g.step_mm;
+    const double t0 = (double)tin, L = (double)tout - (double)tin;
+    const double h = (double)c->h;
+    double tau = 0.0;
+    for (uint64_t k = 0;; ++k) {
+        const double t = (double)k * dl;
+        if (!(t < L)) return 0;
+        const double len = L - t < dl ? L - t : dl;
+        const double s = t0 + t + 0.5 * len;
+        int idx[3];
+        const int n[3] = {c->nx, c->ny, c->nz};
+        for (int a = 0; a < 3; ++a) {
+            const double m = (double)p[a] + (double)d[a] * s;
+            int i = (int)floor((m - (double)P->lo[a]) / h);
+            idx[a] = i < 0 ? 0 : (i > n[a] - 1 ? n[a] - 1 : i);
+        }
+        const size_t v = ((size_t)idx[2] * c->ny + idx[1]) * c->nx + idx[0];
+        const double mu = (double)c->rho[v] * (double)mm[c->ids[v]];
+        (*steps)++;
+        if (tau + mu * len >= tau_star) {
+            const double si = t0 + t + (tau_star - tau) / mu;
+            for (int a = 0; a < 3; ++a) pint[a] = (float)((double)p[a] + (double)d[a] * si);
+            *vox = v;
+            return 1;
+        }
+        tau += mu * len;
+    }
+}
+
 static void mat_mu(const mco_ctx *c, float e, float *mm) {
     for (int m = 0; m < c->n_mat; ++m) {
         const size_t o = (size_t)m * c->J;
@@ -665,6 +712,7 @@ static void tally(const mco_ctx *c, const proj_t *P, const float p[3], const flo
                   float e, int n_int, int64_t *prim, int64_t *scat, mco_stats *st, hist_t *h) {
     int iu, iv;
     if (!panel_pixel(c, P, p, d, &iu, &iv)) { h->end = MCO_END_MISSED; return; }
+    h->pix = iv * c->g.nu + iu;
     float w = lerp_tab(c->t_eta, c->J, e);
     int64_t L = (int64_t)llrintf(w * TALLY_ONE);
     const mco_geometry *g = &c->g;
@@ -685,6 +733,8 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
     rng_t r;
     rng_init(&r, seed, pid);
     h->n_int = 0; h->steps = 0; h->end = MCO_END_MISSED; h->first = MCO_FIRST_NONE;
+    h->x1[0] = h->x1[1] = h->x1[2] = NAN;
+    h->pix = -1;
     st->histories++;
     float e, d[3], p[3], mm[MAX_MAT];
     birth(c, P, &r, &e, d);
@@ -694,16 +744,22 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
     for (;;) {
         float tin, tout;
         if (!box_hit(P, p, d, &tin, &tout)) break;
-        float tau_star = (float)(-log((double)rng_u(&r)));
+        const double u_tau = (double)rng_u(&r);
         st->flights++;
         float pint[3];
         size_t v;
         uint32_t steps = 0;
-        int hit = march(c, P, p, d, tin, tout, mm, tau_star, pint, &v, &steps);
+        int hit;
+        if (c->reading == MCO_READING_PLAIN)
+            hit = march_plain(c, P, p, d, tin, tout, mm, -log(u_tau), pint, &v, &steps);
+        else
+            hit = march(c, P, p, d, tin, tout, mm, (float)(-log(u_tau)), pint, &v, &steps);
         h->steps += steps;
         st->steps += steps;
         if (!hit) break;
         for (int a = 0; a < 3; ++a) p[a] = pint[a];
+        if (!n_int)
+            for (int a = 0; a < 3; ++a) h->x1[a] = pint[a];
         /* interaction type at (material, E): [photo, Rayleigh, Compton] */
         const int m = c->ids[v];
         const size_t o = (size_t)m * c->J;
@@ -717,6 +773,7 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
             if (!n_int) h->first = MCO_FIRST_PHOTO;
             h->end = MCO_END_PHOTO;
             h->n_int = (uint16_t)n_int;
+            h->e_end = e;
             return;
         }
         float ct, e2;
@@ -737,12 +794,14 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
             st->cutoff_kills++;
             h->end = MCO_END_CUTOFF;
             h->n_int = (uint16_t)n_int;
+            h->e_end = e2;
             return;
         }
         if (n_int >= MAX_SCATTER) {
             st->cap_hits++;
             h->end = MCO_END_CAP;
             h->n_int = (uint16_t)n_int;
+            h->e_end = e2;
             return;
         }
         if (e2 != e) {
@@ -751,6 +810,7 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
         }
     }
     h->n_int = (uint16_t)n_int;
+    h->e_end = e;
     tally(c, P, p, d, e, n_int, prim, scat, st, h);
 }
 
@@ -874,6 +934,39 @@ int mco_debug_histories(mco_ctx *c, float beta, uint64_t first, uint64_t m, uint
         if (first_type) first_type[i] = h.first;
     }
     return MCO_OK;
+}
+
+int mco_set_reading(mco_ctx *c, int reading) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (reading != MCO_READING_GRID && reading != MCO_READING_PLAIN)
+        return fail(c, MCO_E_INVALID_ARG, "unknown march reading");
+    c->reading = reading;
+    return MCO_OK;
+}
+
+int mco_debug_paths(mco_ctx *c, float beta, uint64_t first, uint64_t m, uint64_t seed,
+                    float *x_first, int32_t *pixel, float *e_end) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (!isfinite(beta)) return fail(c, MCO_E_INVALID_ARG, "angle must be finite");
+    int rc = ready(c, m);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    for (uint64_t i = 0; i < m; ++i) {
+        hist_t h;
+        history(c, &P, seed, first + i, NULL, NULL, &c->stats, &h);
+        if (x_first)
+            for (int a = 0; a < 3; ++a) x_first[3 * i + a] = h.x1[a];
+        if (pixel) pixel[i] = h.pix;
+        if (e_end) e_end[i] = h.e_end;
+    }
+    return MCO_OK;
+}
+
+void mco_test_rotate(const float d_in[3], float cos_theta, double phi, float d_out[3]) {
+    float d[3] = {d_in[0], d_in[1], d_in[2]};
+    rotate(d, cos_theta, (float)cos(phi), (float)sin(phi));
+    for (int a = 0; a < 3; ++a) d_out[a] = d[a];
 }
 
 int mco_test_sample(mco_ctx *c, int process, int material, float e, uint64_t n, uint64_t seed,

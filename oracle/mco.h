@@ -53,6 +53,13 @@ enum {
     MCO_E_OVERFLOW = -4
 };
 
+/* readings of the fixed-step march (mco_set_reading) */
+enum {
+    MCO_READING_GRID = 0,   /* default: nominal step centres, optical depth on the
+                               2^-32 grid (the transport's specification) */
+    MCO_READING_PLAIN = 1   /* true midpoints of the clipped steps, fp64 depth */
+};
+
 /* geometry flags */
 #define MCO_NO_SCATTER 1u   /* every interaction absorbs (Beer-Lambert check) */
 
@@ -144,6 +151,20 @@ int mco_project_mt(mco_ctx *ctx, float angle_rad, uint64_t n, uint64_t seed,
 int mco_debug_histories(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t m,
                         uint64_t seed, uint16_t *n_int, uint32_t *steps,
                         uint8_t *end_code, uint8_t *first_type);
+
+/* Same histories, other per-history facts for photons [first, first+m):
+ * x_first[3*i..] the first interaction point (NaN if none), pixel[i] the
+ * panel pixel iv*nu+iu the photon crossed (-1 if none), e_end[i] the energy
+ * when the history ended.  Any pointer may be NULL. */
+int mco_debug_paths(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t m, uint64_t seed,
+                    float *x_first, int32_t *pixel, float *e_end);
+
+/* Which reading of the fixed-step march the transport follows. */
+int mco_set_reading(mco_ctx *ctx, int reading);
+
+/* The direction update after a scattering: d_in rotated by polar cosine
+ * cos_theta and azimuth phi (cos/sin taken in fp64, rounded to fp32). */
+void mco_test_rotate(const float d_in[3], float cos_theta, double phi, float d_out[3]);
 
 /* Draws n independent samples of one process (photon ids 0..n-1 of the
  * given seed).  SOURCE_ENERGY: e_out = energy.  SOURCE_DIR: cos_out =

@@ -51,6 +51,17 @@ CASES = [
      "test_oracle_transport.py::test_beer_lambert_slab"),
     ("tally_grid", "int su = iu / (g->nu / g->snu)", "int su = iu % g->snu",
      "test_oracle_transport.py::test_scatter_binning"),
+    ("rotate_azimuth_sign", "cp - uy * sp) / t", "cp + uy * sp) / t",
+     "test_oracle_scatter.py::test_rotation_invariants"),
+    ("rotate_polar_sign", "nz = uz * ct - (st * cp) * t;", "nz = uz * ct + (st * cp) * t;",
+     "test_oracle_scatter.py::test_rotation_invariants"),
+    ("interaction_at_step_start", "float sint = a0 + (float)((ts - tau) / inc * (double)len);",
+     "float sint = a0;", "test_oracle_scatter.py::test_free_path_exponential"),
+    ("scatter_angle_sign", "rotate(d, ct, (float)cos(phi), (float)sin(phi));",
+     "rotate(d, -ct, (float)cos(phi), (float)sin(phi));",
+     "test_oracle_scatter.py::test_single_scatter_brute_force"),
+    ("energy_not_updated", "            e = e2;\n            mat_mu(c, e, mm);",
+     "            mat_mu(c, e2, mm);", "test_oracle_scatter.py::test_single_scatter_brute_force"),
 ]
 
 
