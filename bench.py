@@ -1,12 +1,16 @@
 """Benchmark: photon histories per second of one MC forward projection on one GPU.
 
-Workload (default): 256^3 voxel phantom at 0.5 mm with 20 random ellipsoids of
-water / aluminium / bone-like calcium mix (densities 0.9 - 2.7 g/cm^3) in air,
-150 kVp Kramers spectrum behind 2 mm Al in 1 keV bins, source 500 mm from the
-axis, 512 x 512 panel of 0.4 mm at 1000 mm, 0.5 mm march step, 1e8 photons per
-projection; fp32 transport, int64 fixed-point tallies.  Inputs are resident in
-GPU memory before the timed region.  A "step" is one whole projection:
-clearing both images and the transport kernel over all photons.
+Workload (default, the largest one-GPU configuration): 512^3 voxel phantom at
+0.25 mm with 20 random ellipsoids of water / aluminium / bone-like calcium mix
+(densities 0.9 - 2.7 g/cm^3) and an iron cylinder insert in air, 150 kVp
+Kramers spectrum behind 2 mm Al in 1 keV bins, source 500 mm from the axis,
+2048 x 2048 panel of 0.2 mm at 1000 mm with scatter tallied on 256 x 256,
+0.25 mm march step, 1e9 photons per projection; fp32 transport, int64
+fixed-point tallies.  `--workload ellipsoids256_poly` (256^3, 512^2 panel,
+1e8 photons) and `--workload batch360_uneven16` (the batched launch) are the
+other modes.  Inputs are resident in GPU memory before the timed region.  A
+"step" is one whole projection: clearing both images and the transport kernel
+over all photons.
 
 Output: one JSON line (metric, value, roofline of the transport kernel, CPU
 oracle baseline).  `python bench.py --gpus N` with N > 1 exits: the benchmark
@@ -33,7 +37,14 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # its test against tau* (1)
 ALU_OPS_PER_STEP = 18
 TALLY_BYTES = 8                  # one int64 atomic add per detected photon
-COUNTERS = os.path.join(ROOT, "profiles", "transport_ellipsoids256_poly_counters.json")
+PHANTOMS = {
+    "ellipsoids512_hires": "512^3 voxels at 0.25 mm, 20 random ellipsoids (water, Al, bone-Ca; "
+                           "0.9-2.7 g/cm^3) and an iron cylinder insert (r 5 mm) in air",
+    "ellipsoids256_poly": "256^3 voxels at 0.5 mm, 20 random ellipsoids (water, Al, bone-Ca; "
+                          "0.9-2.7 g/cm^3) in air",
+    "cylinder64": "64^3 voxels at 1 mm, water cylinder r 25 mm in air",
+}
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2201_13191_amd", "csrc", f)
                   for f in ("transport.hip", "kernel_params.hpp")]
 
@@ -46,11 +57,15 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, layout_bytes):
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"transport_{workload}_counters.json")
+
+
+def measured_traffic(workload):
     """HBM bytes per launch from the committed rocprofv3 counter record, if it
     was taken on this exact kernel source and workload; else None."""
     try:
-        rec = json.load(open(COUNTERS))
+        rec = json.load(open(counters_path(workload)))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("workload") != workload:
@@ -62,25 +77,84 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the oracle may use: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS where the host sets it (the CPU share given to one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def _time_oracle(o, w, n, threads):
+    t = time.perf_counter()
+    o.project(w["angle"], n, w["seed"], threads=threads)
+    return time.perf_counter() - t
+
+
 def cpu_baseline(w, seconds):
-    """The oracle, unchanged, on the host cores over a bounded photon sample."""
+    """The oracle, unchanged, on the host cores over a bounded photon sample
+    (photons 0 .. n-1 of the same projection), and on one thread."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     o = oracle.Oracle()
     o.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
     o.set_geometry(**w["geometry"])
     o.set_spectrum(*w["spectrum"])
     n0 = 20_000 * threads
-    t = time.perf_counter()
-    o.project(w["angle"], n0, w["seed"], threads=threads)
-    dt = time.perf_counter() - t
+    dt = _time_oracle(o, w, n0, threads)
     n = int(min(max(n0, n0 * seconds / max(dt, 1e-6)), 1e8))
-    t = time.perf_counter()
-    o.project(w["angle"], n, w["seed"], threads=threads)
-    dt = time.perf_counter() - t
+    dt = _time_oracle(o, w, n, threads)
+    n1 = 20_000
+    dt1 = _time_oracle(o, w, n1, 1)
+    n1 = int(min(max(n1, n1 * (seconds / 4) / max(dt1, 1e-6)), 1e7))
+    dt1 = _time_oracle(o, w, n1, 1)
     return dict(value=n / dt, unit="photon histories/s", cores=threads, kind="oracle",
                 sample=f"photons 0..{n - 1} of the same projection ({n / w['n_photons']:.2%} of "
-                       f"one step), {dt:.1f} s wall on {threads} host threads")
+                       f"one step), {dt:.1f} s wall on {threads} host threads; one thread: "
+                       f"photons 0..{n1 - 1} in {dt1:.1f} s",
+                single_thread=n1 / dt1, cpu_model=cpu_model(), host_cpus=os.cpu_count())
+
+
+def roofline(st, gather_bytes, launch_s, workload, kernel):
+    """The transport kernel against the gather roofline: algorithmic bytes per
+    launch = one voxel lookup of the stored representation per march step
+    (1 B palette code, or 5 B material id + density) plus one 8 B int64 add per
+    detected photon, over the launch's measured duration, against HBM peak.
+    The VALU-issue view (counted march arithmetic per step) is kept beside it."""
+    tallies = st["primary_hits"] + st["scatter_hits"]
+    alg_bytes = st["steps"] * gather_bytes + tallies * TALLY_BYTES
+    gbs = alg_bytes / launch_s / 1e9
+    alg_ops = st["steps"] * ALU_OPS_PER_STEP
+    tops = alg_ops / launch_s / 1e12
+    traffic = measured_traffic(workload)
+    return {
+        "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+        "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_step": gather_bytes,
+        "tally_bytes": TALLY_BYTES, "steps_per_launch": st["steps"],
+        "tallies_per_launch": tallies, "launch_ms": launch_s * 1e3,
+        "steps_per_history": st["steps"] / max(st["histories"], 1),
+        "skipped_fraction": st.get("skipped_steps", 0) / max(st["steps"], 1),
+        "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
+        "alu": {"achieved": tops, "peak": VALU_PEAK_OPS / 1e12, "unit": "T op/s",
+                "frac": tops / (VALU_PEAK_OPS / 1e12), "ops_per_step": ALU_OPS_PER_STEP,
+                "algorithmic_ops_per_launch": alg_ops},
+    }
 
 
 def bench_batch(args):
@@ -113,8 +187,6 @@ def bench_batch(args):
     torch.cuda.synchronize()
     st = g.stats()
     g.stats(False)
-    alg_ops = st["steps"] * ALU_OPS_PER_STEP
-    alg_bytes = st["steps"] + (st["primary_hits"] + st["scatter_hits"]) * TALLY_BYTES
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -128,7 +200,6 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e-3
-    achieved = alg_ops / launch_s / 1e12
     out = {
         "metric": "photon histories/s on 1 GPU (batched persistent launch, hipGraph)",
         "value": n * args.steps / wall, "unit": "photon histories/s", "n_gpus": 1,
@@ -138,13 +209,7 @@ def bench_batch(args):
         "config": {"workload": w["name"], "jobs": len(jobs), "photons_per_step": n,
                    "objects": "256^3 (360 angles x 1e7) + 16 objects 64^3..384^3 at 0.5 mm",
                    "detector": f"{geo['nu']}x{geo['nv']} at {geo['pu_mm']} mm"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "T op/s", "frac": achieved / (VALU_PEAK_OPS / 1e12),
-                     "traffic": None, "kernel": "transport_kernel (batch)",
-                     "algorithmic_ops_per_launch": alg_ops, "ops_per_step": ALU_OPS_PER_STEP,
-                     "launch_ms": launch_s * 1e3,
-                     "gather": {"algorithmic_bytes_per_launch": alg_bytes,
-                                "achieved_GBs": alg_bytes / launch_s / 1e9}},
+        "roofline": roofline(st, 1, launch_s, w["name"], "transport_kernel (batch)"),
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -156,7 +221,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ellipsoids256_poly")
+    ap.add_argument("--workload", default="ellipsoids512_hires")
     ap.add_argument("--photons", type=int, default=0, help="override photons per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
@@ -213,9 +278,6 @@ def main():
     g.stats(False)
     layout, n_pal = g.layout()
     gather_bytes = 1 if layout != mcx.MC_LAYOUT_GENERIC else 5   # bytes per voxel lookup
-    alg_bytes = st["steps"] * gather_bytes + \
-        (st["primary_hits"] + st["scatter_hits"]) * TALLY_BYTES
-    alg_ops = st["steps"] * ALU_OPS_PER_STEP
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):
@@ -235,8 +297,6 @@ def main():
     wall = t1 - t0
     step_ms = [a.elapsed_time(b) for a, b in ev]
     launch_s = float(np.mean(step_ms)) * 1e-3
-    achieved = alg_ops / launch_s / 1e12
-    gather_gbs = alg_bytes / launch_s / 1e9
     log(f"{n * args.steps / wall:.4g} histories/s, {launch_s * 1e3:.2f} ms per step (events), "
         f"steps/history {st['steps'] / max(st['histories'], 1):.1f}")
 
@@ -249,6 +309,26 @@ def main():
         mcx.mc_project(g.ctx, w["angle"], n, w["seed"], pg, sg)
     end_to_end_ms = (time.perf_counter() - t_e) / 2 * 1e3
     log(f"mc_project with host images: {end_to_end_ms:.2f} ms")
+
+    # plain MC's own noise: a second projection with another seed gives the
+    # scatter map's rel-RMS r(n) at n photons (the two maps are independent with
+    # the same mean), so plain MC reaches 2 % at n (r / 0.02)^2 photons
+    p1, s1 = prim.clone(), scat.clone()
+    mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"] + 1, prim, scat, stream)
+    torch.cuda.synchronize()
+    a = s1.double().cpu().numpy().ravel()
+    b = scat.double().cpu().numpy().ravel()
+    d2 = float(((a - b) ** 2).sum())
+    s2 = float((a ** 2).sum() + (b ** 2).sum()) / 2.0 - d2 / 4.0
+    r = float(np.sqrt(d2 / 2.0 / s2)) if s2 > 0 else float("nan")
+    n2 = n * (r / 0.02) ** 2
+    plain_2pct = {"scatter_rel_rms_at_step": r, "photons_for_2pct": n2,
+                  "seconds_for_2pct": n2 / (n * args.steps / wall),
+                  "method": "two independent projections (seeds s, s+1) of the step's photon "
+                            "count; r^2 = (|a-b|^2 / 2) / ((|a|^2 + |b|^2) / 2 - |a-b|^2 / 4)"}
+    log(f"plain MC scatter rel-RMS {r:.4f} at {n:.3g} photons: 2 % needs {n2:.3g} photons, "
+        f"{plain_2pct['seconds_for_2pct']:.2f} s")
+    del p1
 
     # march probe: the fixed-step march of straight rays alone (no physics)
     probe = None
@@ -308,7 +388,7 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds)
 
     out = {
-        "metric": "photon histories/s on 1 GPU (one cone-beam MC projection)",
+        "metric": "photon histories/s on 1 GPU; time to scatter map at \u22642% rel-RMS vs plain MC",
         "value": n * args.steps / wall,
         "unit": "photon histories/s",
         "n_gpus": 1,
@@ -322,9 +402,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload,
-            "phantom": "256^3 voxels at 0.5 mm, 20 random ellipsoids (water, Al, bone-Ca; "
-                       "0.9-2.7 g/cm^3) in air" if args.workload == "ellipsoids256_poly"
-                       else args.workload,
+            "phantom": PHANTOMS.get(args.workload, args.workload),
             "spectrum": f"{len(w['spectrum'][0])} bins",
             "detector": f"{geo['nu']}x{geo['nv']} at {geo['pu_mm']} mm, scatter "
                         f"{geo['snu']}x{geo['snv']}",
@@ -332,26 +410,11 @@ def main():
             "step_mm": geo["step_mm"],
             "tallies": "int64 fixed point",
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "T op/s",
-            "frac": achieved / (VALU_PEAK_OPS / 1e12),
-            "traffic": measured_traffic(args.workload, gather_bytes),
-            "kernel": "transport_kernel",
-            "algorithmic_ops_per_launch": alg_ops,
-            "ops_per_step": ALU_OPS_PER_STEP,
-            "launch_ms": launch_s * 1e3,
-            "steps_per_history": st["steps"] / max(st["histories"], 1),
-            "skipped_fraction": st.get("skipped_steps", 0) / max(st["steps"], 1),
-            "layout": {0: "auto", 1: "palette-lane", 2: "palette-shared", 3: "generic"}[layout],
-            "gather": {"algorithmic_bytes_per_launch": alg_bytes,
-                       "bytes_per_step": gather_bytes, "achieved_GBs": gather_gbs,
-                       "hbm_peak_GBs": HBM_PEAK_GBS, "frac": gather_gbs / HBM_PEAK_GBS},
-            "march_probe": probe,
-            "tally_probe": tally,
-        },
+        "roofline": dict(roofline(st, gather_bytes, launch_s, args.workload, "transport_kernel"),
+                         layout={0: "auto", 1: "palette-lane", 2: "palette-shared",
+                                 3: "generic"}[layout],
+                         march_probe=probe, tally_probe=tally),
+        "time_to_2pct_plain_mc": plain_2pct,
         "cpu_baseline": cpu,
         "end_to_end": {"entry": "mc_project (host images)", "ms": end_to_end_ms,
                        "histories_per_s": n / (end_to_end_ms * 1e-3)},

@@ -124,6 +124,9 @@ struct mc_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<unsigned char> graph_key;
+    // recorded after every batch launch; the next batch call waits on it before it
+    // rewrites the job table and counters, whatever stream either call is on
+    hipEvent_t batch_done = nullptr;
     unsigned generation = 0;             // bumped by every setter
 
     mc_geometry g{};
@@ -457,6 +460,7 @@ void mc_destroy(mc_ctx *c) {
     for (Phantom &ph : c->phantoms) ph.release();
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->batch_done) (void)hipEventDestroy(c->batch_done);
     if (c->d_batch) (void)hipFree(c->d_batch);
     if (c->d_tables) (void)hipFree(c->d_tables);
     if (c->d_ctl) (void)hipFree(c->d_ctl);
@@ -929,6 +933,10 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
         hj[j].grid = jb.phantom;
     }
     unsigned char *db = (unsigned char *)c->d_batch;
+    if (!c->batch_done)
+        HIP_TRY(c, hipEventCreateWithFlags(&c->batch_done, hipEventDisableTiming));
+    else
+        HIP_TRY(c, hipStreamWaitEvent(s, c->batch_done, 0));
     HIP_TRY(c, hipMemcpyAsync(db, host.data(), gb + jbytes, hipMemcpyHostToDevice, s));
 
     KParams p;
@@ -954,14 +962,17 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
                                     (size_t)n_jobs, s);
         if (e == hipSuccess) e = launch_batch(p, max_lane_pal, grid, block, stats, s);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+        HIP_TRY(c, hipEventRecord(c->batch_done, s));
         return MC_OK;
     }
     // graph: clear kernel -> persistent transport kernel, captured once per
     // (buffers, shape, state) and replayed; the job table is uploaded above
-    std::vector<unsigned char> key(sizeof(KParams) + 4 * sizeof(uint64_t));
+    std::vector<unsigned char> key(sizeof(KParams) + 5 * sizeof(uint64_t));
     std::memcpy(key.data(), &p, sizeof p);
-    const uint64_t extra[4] = {out_elems, (uint64_t)grid, (uint64_t)block,
-                               ((uint64_t)c->generation << 8) | (uint64_t)max_lane_pal};
+    // the captured clear kernel writes through d_out, so the buffer is part of the key
+    const uint64_t extra[5] = {out_elems, (uint64_t)grid, (uint64_t)block,
+                               ((uint64_t)c->generation << 8) | (uint64_t)max_lane_pal,
+                               (uint64_t)(uintptr_t)d_out};
     std::memcpy(key.data() + sizeof p, extra, sizeof extra);
     if (!c->graph_exec || key != c->graph_key) {
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -985,6 +996,7 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
         c->graph_key = key;
     }
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+    HIP_TRY(c, hipEventRecord(c->batch_done, s));
     return MC_OK;
 }
 

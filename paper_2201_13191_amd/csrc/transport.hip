@@ -305,6 +305,9 @@ constexpr uint32_t kMinSkip = 4;             // shortest run taken at once
 #define MCX_PREFETCH 8
 #endif
 constexpr int kPrefetch = MCX_PREFETCH;   // march steps whose voxel loads are issued together
+// An unclamped group reads up to kPrefetch - 1 step centres past a flight's last
+// step; with steps of at most one voxel those lie within the edge copies.
+static_assert(kPrefetch + 1 <= kEdgePad, "unclamped gathers would read past the edge copies");
 constexpr int kLdsHeader = 256 + 64;   // floats: palette densities, then 256 palette ids
 
 // the value lane `src` (wave-uniform) holds, read into a scalar register

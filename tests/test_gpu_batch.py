@@ -109,6 +109,38 @@ def test_batch_equals_single_projections(torch_gpu):
     rp, rs = singles[j["phantom"]].project(j["angle_rad"], j["n_photons"], j["seed"])
     assert np.array_equal(host[j["primary_offset"]:j["primary_offset"] + np_].reshape(rp.shape), rp)
 
+    # the same graph key with another output buffer of the same size: the replay
+    # must clear and fill the new buffer and leave the previous one alone
+    say("batch graph into a second buffer")
+    mcx.mc_project_batch(g.ctx, jobs, out, total, flags=mcx.MC_BATCH_GRAPH, stream=stream)
+    torch.cuda.synchronize()
+    check("graph before switch")
+    before = out.clone()
+    out2 = torch.full((total,), 77, dtype=torch.int64, device=dev)
+    mcx.mc_project_batch(g.ctx, jobs, out2, total, flags=mcx.MC_BATCH_GRAPH, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(out, before)
+    out, out2 = out2, out
+    check("graph second buffer")
+
+    # back-to-back batches on two streams share the context's job table: the
+    # second call waits for the first before rewriting it
+    say("batch on two streams")
+    s2 = torch.cuda.Stream()
+    out2.fill_(9)
+    out.fill_(-3)
+    torch.cuda.synchronize()
+    mcx.mc_project_batch(g.ctx, jobs, out2, total, flags=0, stream=stream)
+    mcx.mc_project_batch(g.ctx, jobs2, out, total, flags=0, stream=s2)
+    torch.cuda.synchronize()
+    out, out2 = out2, out
+    check("first stream")
+    host2 = out2.cpu().numpy()
+    for j in (jobs2[4], jobs2[11]):
+        rp, rs = singles[j["phantom"]].project(j["angle_rad"], j["n_photons"], j["seed"])
+        assert np.array_equal(host2[j["primary_offset"]:j["primary_offset"] + np_].reshape(rp.shape), rp)
+        assert np.array_equal(host2[j["scatter_offset"]:j["scatter_offset"] + ns_].reshape(rs.shape), rs)
+
     # two jobs against the oracle
     for j in (jobs[4], jobs[7]):
         a, b, h = ph[j["phantom"]]

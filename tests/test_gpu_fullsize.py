@@ -75,3 +75,42 @@ def test_full_size_workload(torch_gpu, name):
     po, so = o.project_range(w["angle"], a, m, w["seed"])
     check_images(f"{name}[{a}:{a + m}]", pr.cpu().numpy(), sr.cpu().numpy(), po, so)
     g.close()
+
+
+def _host_threads():
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def test_full_image_256_equals_oracle(torch_gpu):
+    """The whole 1e8-photon projection of the 256^3 polychromatic workload,
+    every pixel of both images, against the oracle's image of the same photons
+    (threaded over photon ranges, which sums to the sequential oracle's image)."""
+    torch = torch_gpu
+    w = inputs.workload("ellipsoids256_poly")
+    n, geo = w["n_photons"], w["geometry"]
+    g = mcx.Projector(0)
+    o = oracle.Oracle()
+    for side in (g, o):
+        side.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
+        side.set_geometry(**geo)
+        side.set_spectrum(*w["spectrum"])
+    p = torch.empty((geo["nv"], geo["nu"]), dtype=torch.int64, device="cuda:0")
+    s = torch.empty((geo["snv"], geo["snu"]), dtype=torch.int64, device="cuda:0")
+    say("ellipsoids256_poly whole image on the GPU", n)
+    mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"], p, s)
+    torch.cuda.synchronize()
+    threads = _host_threads()
+    say("ellipsoids256_poly whole image on the oracle,", threads, "threads")
+    po, so = o.project(w["angle"], n, w["seed"], threads=threads)
+    pg, sg = p.cpu().numpy(), s.cpu().numpy()
+    check_images("ellipsoids256_poly whole image", pg, sg, po, so)
+    say("bitwise", bool(np.array_equal(pg, po) and np.array_equal(sg, so)))
+    g.close()
