@@ -20,6 +20,7 @@ PROC_SOURCE_ENERGY, PROC_RAYLEIGH, PROC_COMPTON, PROC_SOURCE_DIR = 0, 1, 2, 3
 END_PRIMARY, END_SCATTER, END_MISSED, END_PHOTO, END_CUTOFF, END_CAP = range(6)
 FIRST_NONE, FIRST_PHOTO, FIRST_RAYLEIGH, FIRST_COMPTON = range(4)
 READING_GRID, READING_PLAIN = 0, 1
+SCORE_ANALOG, SCORE_POINT = 0, 1
 
 
 class Material(C.Structure):
@@ -38,7 +39,8 @@ class Geometry(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "histories", "steps", "flights", "photo", "rayleigh", "compton",
-        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits")]
+        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits",
+        "pd_scores", "pd_killed", "pd_steps")]
 
 
 _lib = None
@@ -71,6 +73,11 @@ def lib():
         L.mco_debug_paths.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, C.c_uint64,
                                       P, P, P]
         L.mco_set_reading.argtypes = [P, C.c_int]
+        L.mco_set_estimator.argtypes = [P, C.c_int, C.c_int, C.c_double]
+        L.mco_pd_pdf.argtypes = [P, C.c_int, C.c_int, C.c_float, C.c_double,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_float)]
+        L.mco_pd_score_event.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, C.c_int, P, P,
+                                         C.c_float, C.c_int, C.c_int, P]
         L.mco_test_rotate.argtypes = [P, C.c_float, C.c_double, P]
         L.mco_test_rotate.restype = None
         L.mco_test_sample.argtypes = [P, C.c_int, C.c_int, C.c_float, C.c_uint64,
@@ -203,6 +210,32 @@ class Oracle:
 
     def set_reading(self, reading):
         self._check(self._L.mco_set_reading(self._h, reading))
+
+    def set_estimator(self, mode, split=1, rr_kev=0.0):
+        """SCORE_ANALOG, or SCORE_POINT: the point-detector estimator of eq.
+        (3)-(5) with `split` pseudo-particles per scattering and Russian
+        roulette below rr_kev (0: off)."""
+        self._check(self._L.mco_set_estimator(self._h, mode, split, float(rr_kev)))
+
+    def pd_pdf(self, process, material, e_kev, lam):
+        """(pdf per unit scattering cosine, scattered energy) of the point
+        detector's angular law for PROC_RAYLEIGH or PROC_COMPTON."""
+        pdf, e2 = C.c_double(), C.c_float()
+        self._check(self._L.mco_pd_pdf(self._h, process, material, e_kev, float(lam),
+                                       C.byref(pdf), C.byref(e2)))
+        return pdf.value, e2.value
+
+    def pd_score_event(self, angle, seed, pid, n_prior, o, d, e_kev, material, process,
+                       scatter=None):
+        """Adds one scattering event's point-detector scores to a scatter image."""
+        if scatter is None:
+            scatter = self._images()[1]
+        o = np.ascontiguousarray(o, dtype=np.float32)
+        d = np.ascontiguousarray(d, dtype=np.float32)
+        self._check(self._L.mco_pd_score_event(self._h, angle, seed, pid, n_prior, _ptr(o),
+                                               _ptr(d), e_kev, material, process,
+                                               _ptr(scatter)))
+        return scatter
 
     def test_sample(self, process, material, e_kev, n, seed):
         cos = np.zeros(n, np.float32)

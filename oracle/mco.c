@@ -75,6 +75,9 @@ struct mco_ctx {
     float *t_pe, *t_coh, *t_inc, *t_eta;
     int tables_dirty;
     int reading;                /* MCO_READING_GRID or MCO_READING_PLAIN */
+    int estimator;              /* MCO_SCORE_ANALOG or MCO_SCORE_POINT   */
+    int split;                  /* pseudo-particles per scattering event  */
+    double rr_kev;              /* Russian-roulette threshold (0: none)   */
     mco_stats stats;
 };
 
@@ -241,6 +244,7 @@ int mco_create(mco_ctx **out) {
     mco_ctx *c = (mco_ctx *)calloc(1, sizeof *c);
     if (!c) return MCO_E_OOM;
     set_mats(c, DEFAULT_MATS, 5);
+    c->split = 1;
     *out = c;
     return MCO_OK;
 }
@@ -612,7 +616,7 @@ static double on_grid(double x) { return ldexp(rint(ldexp(x, 32)), -32); }
  * with the interaction point and voxel. */
 static int march(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
                  float tin, float tout, const float *mm, float tau_star, float pint[3],
-                 size_t *vox, uint32_t *steps) {
+                 size_t *vox, uint32_t *steps, double *tau_exit) {
     const float dl = c->g.step_mm;
     float pin[3], c0[3], G[3], q[3];
     for (int a = 0; a < 3; ++a) pin[a] = p[a] + d[a] * tin;
@@ -625,7 +629,10 @@ static int march(const mco_ctx *c, const proj_t *P, const float p[3], const floa
     double tau = 0.0;
     for (uint32_t k = 0;; ++k) {
         float a0 = (float)k * dl;
-        if (!(a0 < L)) return 0;
+        if (!(a0 < L)) {
+            if (tau_exit) *tau_exit = tau;
+            return 0;
+        }
         for (int a = 0; a < 3; ++a)
             q[a] = (k & 3u) == 0u ? c0[a] + (float)k * G[a] : q[a] + G[a];
         int ix = (int)q[0];
@@ -668,14 +675,17 @@ static int march(const mco_ctx *c, const proj_t *P, const float p[3], const floa
  * one (selected by mco_set_reading). */
 static int march_plain(const mco_ctx *c, const proj_t *P, const float p[3], const float d[3],
                        float tin, float tout, const float *mm, double tau_star, float pint[3],
-                       size_t *vox, uint32_t *steps) {
+                       size_t *vox, uint32_t *steps, double *tau_exit) {
     const double dl = (double)c->g.step_mm;
     const double t0 = (double)tin, L = (double)tout - (double)tin;
     const double h = (double)c->h;
     double tau = 0.0;
     for (uint64_t k = 0;; ++k) {
         const double t = (double)k * dl;
-        if (!(t < L)) return 0;
+        if (!(t < L)) {
+            if (tau_exit) *tau_exit = tau;
+            return 0;
+        }
         const double len = L - t < dl ? L - t : dl;
         const double s = t0 + t + 0.5 * len;
         int idx[3];
@@ -722,9 +732,131 @@ static void tally(const mco_ctx *c, const proj_t *P, const float p[3], const flo
         h->end = MCO_END_PRIMARY;
     } else {
         int su = iu / (g->nu / g->snu), sv = iv / (g->nv / g->snv);
-        if (scat) scat[(size_t)sv * g->snu + su] += L;
+        /* with the point-detector estimator the scatter image holds its scores only */
+        if (scat && c->estimator == MCO_SCORE_ANALOG) scat[(size_t)sv * g->snu + su] += L;
         st->scatter_hits++;
         h->end = MCO_END_SCATTER;
+    }
+}
+
+/* ------------------------------------------------------------ point detector
+ * The scorer of eq. (3)-(5) with splitting and Russian roulette (section
+ * II-C-1).  At every Compton or Rayleigh event the photon is split into
+ * `split` pseudo-particles; each picks a random point on the panel (the
+ * random pixel of the paper, with a uniform position inside it) and scores
+ * the expected energy that reaches that point straight from the event:
+ *
+ *   x = eta(E') p(lambda) cos(gamma) A / (2 pi d^2 split) * exp(-tau),
+ *
+ * p(lambda) the pdf per unit scattering cosine of the event's process
+ * (eq. (4) Compton, eq. (5) Rayleigh), lambda the cosine between the photon's
+ * incoming direction and the direction to the point, d the distance, gamma the
+ * angle of that direction to the panel normal, A the panel area (the point's
+ * density is 1/A), E' the energy scattered towards the point, and tau the
+ * optical depth at E' from the event to the box exit, marched with the same
+ * fixed-step rule as the transport.  eq. (3) is the flux of a point detector
+ * per unit area normal to the ray; cos(gamma) turns it into the flux through
+ * the panel, so the expectation equals the analog scatter image's.  A
+ * pseudo-particle whose unattenuated score x0 is below the threshold survives
+ * with probability x0 / threshold and then scores with x0 = threshold (the
+ * roulette of section II-C-1, unbiased), before its march is paid for.
+ *
+ * Each pseudo-particle i of the photon's n-th scattering (n counted from 0)
+ * draws from its own Philox block, counter (photon id, n, i + 1) -- the
+ * analog draws use counters ending in 0 -- so the photon's own history is the
+ * same with and without this scorer. */
+
+/* the integral over the scattering cosine of the bracket of eq. (1) with
+ * S = 1: sigma_KN / (pi r_e^2) */
+static double kn_norm(float e) {
+    return (double)(sigma_kn_l((long double)e) / (PI_L * R_E_CM * R_E_CM));
+}
+
+/* pdf per unit scattering cosine `lam` of the process at energy e in
+ * material m (the one its sampler draws from), and the energy scattered
+ * into that direction */
+static double pd_pdf(const mco_ctx *c, int proc, int m, float e, double lam, float *e_out) {
+    if (proc == MCO_PROC_COMPTON) {
+        const double alpha = (double)e / MEC2_KEV;
+        const double ratio = 1.0 + alpha * (1.0 - lam);     /* E / E' = alpha / alpha' */
+        const double r = 1.0 / ratio;
+        *e_out = (float)((double)e / ratio);
+        return r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(e);
+    }
+    /* Rayleigh: (1 + lam^2) F^2 with F = Z / (1 + b x^2)^2, x^2 = (1 - lam)/2 / wavelength^2;
+     * over lam in [-1, 1] the unnormalised density integrates to 2 Z^2 G(b V) */
+    const double t = (double)e / HC_KEV_A;
+    const double V = t * t;
+    const double w = 1.0 + c->rayl_b[m] * ((1.0 - lam) * 0.5 * V);
+    *e_out = e;
+    return (1.0 + lam * lam) / (((w * w) * w) * w) /
+           (2.0 * (double)coh_g((long double)(c->rayl_b[m] * V)));
+}
+
+static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t pid, int n,
+                     const float o[3], const float d[3], float e, int m, int proc,
+                     int64_t *scat, mco_stats *st) {
+    if (n + 1 >= MAX_SCATTER) return;     /* the scattered photon is not transported */
+    const mco_geometry *g = &c->g;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const double area = (double)((float)g->nu * g->pu_mm) * (double)((float)g->nv * g->pv_mm);
+    for (int i = 0; i < c->split; ++i) {
+        const uint32_t ctr[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), (uint32_t)n,
+                                 (uint32_t)i + 1u};
+        uint32_t w[4];
+        mco_philox4x32_10(ctr, key, w);
+        /* the random point on the panel, in pixel units, and its pixel */
+        const float fu = uniform01(w[0]) * (float)g->nu;
+        const float fv = uniform01(w[1]) * (float)g->nv;
+        int iu = (int)fu, iv = (int)fv;
+        if (iu > g->nu - 1) iu = g->nu - 1;
+        if (iv > g->nv - 1) iv = g->nv - 1;
+        const float uu = fu * g->pu_mm - P->hu, vv = fv * g->pv_mm - P->hv;
+        float q[3], dq[3];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = (P->D[a] + uu * P->eu[a]) + vv * P->ev[a];
+            dq[a] = q[a] - o[a];
+        }
+        const double r2 = ((double)dq[0] * dq[0] + (double)dq[1] * dq[1]) + (double)dq[2] * dq[2];
+        const double dist = sqrt(r2);
+        double lam = (((double)d[0] * dq[0] + (double)d[1] * dq[1]) + (double)d[2] * dq[2]) / dist;
+        lam = lam > 1.0 ? 1.0 : (lam < -1.0 ? -1.0 : lam);
+        const double cg =
+            (((double)P->ax[0] * dq[0] + (double)P->ax[1] * dq[1]) + (double)P->ax[2] * dq[2]) /
+            dist;
+        float e2;
+        const double pdf = pd_pdf(c, proc, m, e, lam, &e2);
+        if (e2 < E_CUT_KEV) continue;       /* such a photon would be killed */
+        const double eta = (double)lerp_tab(c->t_eta, c->J, e2);
+        double x0 = (((eta * pdf) * cg) * area) / ((TWO_PI_D * r2) * (double)c->split);
+        if (c->rr_kev > 0.0 && x0 < c->rr_kev) {
+            if ((double)uniform01(w[2]) < x0 / c->rr_kev) {
+                x0 = c->rr_kev;
+            } else {
+                st->pd_killed++;
+                continue;
+            }
+        }
+        /* attenuation from the event to the box exit at E' */
+        float om[3];
+        for (int a = 0; a < 3; ++a) om[a] = (float)((double)dq[a] / dist);
+        double tau = 0.0;
+        float tin, tout;
+        if (box_hit(P, o, om, &tin, &tout)) {
+            float mm[MAX_MAT], pint[3];
+            size_t v;
+            uint32_t steps = 0;
+            mat_mu(c, e2, mm);
+            if (c->reading == MCO_READING_PLAIN)
+                (void)march_plain(c, P, o, om, tin, tout, mm, INFINITY, pint, &v, &steps, &tau);
+            else
+                (void)march(c, P, o, om, tin, tout, mm, INFINITY, pint, &v, &steps, &tau);
+            st->pd_steps += steps;
+        }
+        const double x = x0 * exp(-tau);
+        const int64_t L = (int64_t)llrint(x * 1048576.0);
+        scat[(size_t)(iv / (g->nv / g->snv)) * g->snu + (size_t)(iu / (g->nu / g->snu))] += L;
+        st->pd_scores++;
     }
 }
 
@@ -751,9 +883,9 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
         uint32_t steps = 0;
         int hit;
         if (c->reading == MCO_READING_PLAIN)
-            hit = march_plain(c, P, p, d, tin, tout, mm, -log(u_tau), pint, &v, &steps);
+            hit = march_plain(c, P, p, d, tin, tout, mm, -log(u_tau), pint, &v, &steps, NULL);
         else
-            hit = march(c, P, p, d, tin, tout, mm, (float)(-log(u_tau)), pint, &v, &steps);
+            hit = march(c, P, p, d, tin, tout, mm, (float)(-log(u_tau)), pint, &v, &steps, NULL);
         h->steps += steps;
         st->steps += steps;
         if (!hit) break;
@@ -788,6 +920,9 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
             if (!n_int) h->first = MCO_FIRST_COMPTON;
         }
         double phi = TWO_PI_D * (double)rng_u(&r);
+        if (c->estimator == MCO_SCORE_POINT && scat)
+            pd_event(c, P, seed, pid, n_int, p, d, e, m,
+                     x < pe + coh ? MCO_PROC_RAYLEIGH : MCO_PROC_COMPTON, scat, st);
         rotate(d, ct, (float)cos(phi), (float)sin(phi));
         n_int++;
         if (e2 < E_CUT_KEV) {
@@ -842,6 +977,7 @@ static void stats_add(mco_stats *a, const mco_stats *b) {
     a->photo += b->photo; a->rayleigh += b->rayleigh; a->compton += b->compton;
     a->primary_hits += b->primary_hits; a->scatter_hits += b->scatter_hits;
     a->cutoff_kills += b->cutoff_kills; a->cap_hits += b->cap_hits;
+    a->pd_scores += b->pd_scores; a->pd_killed += b->pd_killed; a->pd_steps += b->pd_steps;
 }
 
 int mco_project_range(mco_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t seed,
@@ -1020,3 +1156,47 @@ int mco_get_stats(mco_ctx *c, mco_stats *out) {
 }
 
 double mco_tally_scale(void) { return 1.0 / 1048576.0; }
+
+int mco_set_estimator(mco_ctx *c, int mode, int split, double rr_kev) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (mode != MCO_SCORE_ANALOG && mode != MCO_SCORE_POINT)
+        return fail(c, MCO_E_INVALID_ARG, "unknown estimator");
+    if (split < 1 || split > 1024) return fail(c, MCO_E_INVALID_ARG, "split must be 1..1024");
+    if (!(rr_kev >= 0.0) || !isfinite(rr_kev))
+        return fail(c, MCO_E_INVALID_ARG, "roulette threshold must be finite and >= 0");
+    c->estimator = mode;
+    c->split = split;
+    c->rr_kev = rr_kev;
+    return MCO_OK;
+}
+
+int mco_pd_pdf(mco_ctx *c, int process, int material, float e_kev, double lambda, double *pdf,
+               float *e_out) {
+    if (!c || !pdf) return MCO_E_INVALID_ARG;
+    if (process != MCO_PROC_RAYLEIGH && process != MCO_PROC_COMPTON)
+        return fail(c, MCO_E_INVALID_ARG, "process must be Rayleigh or Compton");
+    if (material < 0 || material >= c->n_mat || !(e_kev >= 1.0f && e_kev <= 1000.0f) ||
+        !(lambda >= -1.0 && lambda <= 1.0))
+        return fail(c, MCO_E_INVALID_ARG, "bad material, energy or cosine");
+    float e2;
+    *pdf = pd_pdf(c, process, material, e_kev, lambda, &e2);
+    if (e_out) *e_out = e2;
+    return MCO_OK;
+}
+
+int mco_pd_score_event(mco_ctx *c, float beta, uint64_t seed, uint64_t pid, int n_prior,
+                       const float o[3], const float d[3], float e_kev, int material,
+                       int process, int64_t *scatter) {
+    if (!c || !o || !d || !scatter) return MCO_E_INVALID_ARG;
+    if (process != MCO_PROC_RAYLEIGH && process != MCO_PROC_COMPTON)
+        return fail(c, MCO_E_INVALID_ARG, "process must be Rayleigh or Compton");
+    if (material < 0 || material >= c->n_mat || !(e_kev >= 1.0f && e_kev <= 1000.0f) ||
+        n_prior < 0)
+        return fail(c, MCO_E_INVALID_ARG, "bad material, energy or event index");
+    int rc = ready(c, 1);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    pd_event(c, &P, seed, pid, n_prior, o, d, e_kev, material, process, scatter, &c->stats);
+    return MCO_OK;
+}

@@ -23,10 +23,10 @@
  * interaction, the quantity of eq. (7)) or scatter (>= 1 interaction, the
  * quantity of eq. (6)), weighted by the detector energy response eta(E).
  *
- * The scoring here is analog (each detected photon scores once in the pixel
- * it crosses); the paper's point-detector estimator of eq. (3)-(5) is a
- * variance-reduced estimator of the same expectation and is not part of
- * this oracle.
+ * The default scoring is analog (each detected photon scores once in the
+ * pixel it crosses); the paper's point-detector estimator of eq. (3)-(5),
+ * with splitting and Russian roulette (section II-C-1), is a selectable
+ * variance-reduced estimator of the same expectation (mco_set_estimator).
  *
  * Because the algorithm is stochastic, exactness is defined per seed: the
  * random draw order, the floating-point precision of every operation and the
@@ -58,6 +58,14 @@ enum {
     MCO_READING_GRID = 0,   /* default: nominal step centres, optical depth on the
                                2^-32 grid (the transport's specification) */
     MCO_READING_PLAIN = 1   /* true midpoints of the clipped steps, fp64 depth */
+};
+
+/* scatter estimators (mco_set_estimator) */
+enum {
+    MCO_SCORE_ANALOG = 0,   /* each scattered photon that crosses the panel scores
+                               in the pixel it crosses */
+    MCO_SCORE_POINT = 1     /* point-detector scores of eq. (3)-(5) at every
+                               scattering, with splitting and Russian roulette */
 };
 
 /* geometry flags */
@@ -114,6 +122,9 @@ typedef struct mco_stats {
     uint64_t photo, rayleigh, compton;
     uint64_t primary_hits, scatter_hits;
     uint64_t cutoff_kills, cap_hits;
+    uint64_t pd_scores;    /* point-detector pseudo-particles scored  */
+    uint64_t pd_killed;    /* ... removed by Russian roulette         */
+    uint64_t pd_steps;     /* march steps of their attenuation chords */
 } mco_stats;
 
 typedef struct mco_ctx mco_ctx;
@@ -158,6 +169,28 @@ int mco_debug_histories(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t 
  * when the history ended.  Any pointer may be NULL. */
 int mco_debug_paths(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t m, uint64_t seed,
                     float *x_first, int32_t *pixel, float *e_end);
+
+/* Scatter estimator: MCO_SCORE_ANALOG (default) or MCO_SCORE_POINT, the
+ * point-detector estimator of eq. (3)-(5) (section II-A) with `split`
+ * pseudo-particles per scattering event (1..1024) and Russian roulette below
+ * rr_kev (keV; 0 turns it off) (section II-C-1).  With MCO_SCORE_POINT the
+ * scatter image holds the estimator's scores (same expectation as the analog
+ * image); the primary image and every photon's history are unchanged. */
+int mco_set_estimator(mco_ctx *ctx, int mode, int split, double rr_kev);
+
+/* The point-detector scorer's angular pdf per unit scattering cosine
+ * (eq. (4) for MCO_PROC_COMPTON, eq. (5) for MCO_PROC_RAYLEIGH) at energy
+ * e_kev in `material`, and the energy scattered into that cosine. */
+int mco_pd_pdf(mco_ctx *ctx, int process, int material, float e_kev, double lambda,
+               double *pdf, float *e_out);
+
+/* Adds to scatter[snv*snu] the point-detector scores of one scattering
+ * event: photon pid of `seed`, its n_prior-th scattering (from 0), at point
+ * o with incoming direction d and energy e_kev in `material`, by `process`
+ * (the estimator's split and roulette settings apply). */
+int mco_pd_score_event(mco_ctx *ctx, float angle_rad, uint64_t seed, uint64_t pid,
+                       int n_prior, const float o[3], const float d[3], float e_kev,
+                       int material, int process, int64_t *scatter);
 
 /* Which reading of the fixed-step march the transport follows. */
 int mco_set_reading(mco_ctx *ctx, int reading);

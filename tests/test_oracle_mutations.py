@@ -62,6 +62,23 @@ CASES = [
      "test_oracle_scatter.py::test_single_scatter_brute_force"),
     ("energy_not_updated", "            e = e2;\n            mat_mu(c, e, mm);",
      "            mat_mu(c, e2, mm);", "test_oracle_scatter.py::test_single_scatter_brute_force"),
+    # the point-detector estimator (eq. (3)-(5), section II-C-1)
+    ("pd_cos_gamma", "* pdf) * cg) * area)", "* pdf) * 1.0) * area)",
+     "test_oracle_pd.py::test_pd_vacuum_event_integral"),
+    ("pd_lambda_sign", "(double)d[2] * dq[2]) / dist;", "(double)d[2] * dq[2]) / -dist;",
+     "test_oracle_pd.py::test_pd_vacuum_event_integral"),
+    ("pd_split_norm", "* (double)c->split);", ");",
+     "test_oracle_pd.py::test_pd_vacuum_event_integral"),
+    ("pd_response_at_incoming_energy", "lerp_tab(c->t_eta, c->J, e2);",
+     "lerp_tab(c->t_eta, c->J, e);", "test_oracle_pd.py::test_pd_vacuum_event_integral"),
+    ("pd_mu_at_incoming_energy", "mat_mu(c, e2, mm);", "mat_mu(c, e, mm);",
+     "test_oracle_pd.py::test_pd_event_attenuated_integral"),
+    ("pd_roulette_weight", "x0 = c->rr_kev;", "x0 = x0 * 1.0;",
+     "test_oracle_pd.py::test_pd_matches_analog_expectation"),
+    ("pd_rayleigh_norm", "(2.0 * (double)coh_g(", "(1.0 * (double)coh_g(",
+     "test_oracle_pd.py::test_pd_pdf_rayleigh"),
+    ("pd_attenuation", "x0 * exp(-tau)", "x0 * exp(-0.5 * tau)",
+     "test_oracle_pd.py::test_pd_single_scatter_brute_force"),
 ]
 
 
