@@ -74,6 +74,8 @@ def lib():
                                       P, P, P]
         L.mco_set_reading.argtypes = [P, C.c_int]
         L.mco_set_estimator.argtypes = [P, C.c_int, C.c_int, C.c_double]
+        L.mco_primary_expected.argtypes = [P, C.c_float, C.c_int, P]
+        L.mco_interp_angles.argtypes = [P, C.c_int, C.c_int64, P]
         L.mco_pd_pdf.argtypes = [P, C.c_int, C.c_int, C.c_float, C.c_double,
                                  C.POINTER(C.c_double), C.POINTER(C.c_float)]
         L.mco_pd_score_event.argtypes = [P, C.c_float, C.c_uint64, C.c_uint64, C.c_int, P, P,
@@ -217,6 +219,13 @@ class Oracle:
         roulette below rr_kev (0: off)."""
         self._check(self._L.mco_set_estimator(self._h, mode, split, float(rr_kev)))
 
+    def primary_expected(self, angle, sub=2):
+        """Eq. (7): expected primary tally per emitted photon (keV), [nv][nu] fp64."""
+        g = self.geometry
+        out = np.zeros((g["nv"], g["nu"]), np.float64)
+        self._check(self._L.mco_primary_expected(self._h, angle, sub, _ptr(out)))
+        return out
+
     def pd_pdf(self, process, material, e_kev, lam):
         """(pdf per unit scattering cosine, scattered energy) of the point
         detector's angular law for PROC_RAYLEIGH or PROC_COMPTON."""
@@ -305,3 +314,15 @@ def rotate(d, cos_theta, phi):
 
 def tally_scale():
     return lib().mco_tally_scale()
+
+
+def interp_angles(sim):
+    """Every-other-angle scatter maps [n_sim, ...] -> the full set [2 n_sim, ...]."""
+    sim = np.ascontiguousarray(sim, dtype=np.float32)
+    n_sim = sim.shape[0]
+    n_pix = sim[0].size
+    full = np.zeros((2 * n_sim,) + sim.shape[1:], np.float32)
+    rc = lib().mco_interp_angles(_ptr(sim), n_sim, n_pix, _ptr(full))
+    if rc:
+        raise OracleError(rc, "interp_angles")
+    return full

@@ -1200,3 +1200,122 @@ int mco_pd_score_event(mco_ctx *c, float beta, uint64_t seed, uint64_t pid, int 
     pd_event(c, &P, seed, pid, n_prior, o, d, e_kev, material, process, scatter, &c->stats);
     return MCO_OK;
 }
+
+/* ------------------------------------------------------------ deterministic primary
+ * Eq. (7): the primary intensity as an integral over the spectrum of
+ * eta(E) exp(-mu(E) L) along the ray from the source to the detector, here for
+ * each pixel as the expectation of the analog primary tally per emitted
+ * photon: the spectrum is the bins' draw probabilities (thresholds of the
+ * sampler), the source's photons per steradian are 1 / Omega_cone (the cone
+ * circumscribing the panel, with the sampler's fp32 1 - cos(theta_max)), and
+ * the pixel is integrated over sub x sub sub-pixels by the midpoint rule with
+ * d(Omega) = cos(gamma) dA / R^2.  Each sub-pixel ray from the source is
+ * marched with the transport's fixed-step rule (nominal step centres, last
+ * step clipped) and collects rho * length per material, Lambda_m (fp64), so
+ * that mu(E) L = sum_m Lambda_m mu_m(E) / rho with the transport's tables.
+ * Where eq. (7) writes 1/d^2, the pixel's solid angle cos(gamma) dA / R^2
+ * stands (the paper leaves the pixel area and obliquity out). */
+static void ray_lambda(const mco_ctx *c, const proj_t *P, const float d[3], double *lam) {
+    for (int m = 0; m < c->n_mat; ++m) lam[m] = 0.0;
+    float tin, tout;
+    if (!box_hit(P, P->S, d, &tin, &tout)) return;
+    const float dl = c->g.step_mm;
+    float pin[3], c0[3], G[3], q[3];
+    for (int a = 0; a < 3; ++a) pin[a] = P->S[a] + d[a] * tin;
+    const float L = tout - tin;
+    for (int a = 0; a < 3; ++a) {
+        G[a] = (d[a] * P->inv_h) * dl;
+        c0[a] = (pin[a] - P->lo[a]) * P->inv_h + 0.5f * G[a];
+    }
+    for (uint32_t k = 0;; ++k) {
+        const float a0 = (float)k * dl;
+        if (!(a0 < L)) return;
+        for (int a = 0; a < 3; ++a)
+            q[a] = (k & 3u) == 0u ? c0[a] + (float)k * G[a] : q[a] + G[a];
+        int ix = (int)q[0], iy = (int)q[1], iz = (int)q[2];
+        ix = ix < 0 ? 0 : (ix > c->nx - 1 ? c->nx - 1 : ix);
+        iy = iy < 0 ? 0 : (iy > c->ny - 1 ? c->ny - 1 : iy);
+        iz = iz < 0 ? 0 : (iz > c->nz - 1 ? c->nz - 1 : iz);
+        const size_t v = ((size_t)iz * c->ny + iy) * c->nx + ix;
+        const double len = (float)(k + 1u) * dl < L ? (double)dl : (double)(L - a0);
+        lam[c->ids[v]] += (double)c->rho[v] * len;
+    }
+}
+
+int mco_primary_expected(mco_ctx *c, float beta, int sub, double *out) {
+    if (!c || !out) return MCO_E_INVALID_ARG;
+    if (sub < 1 || sub > 64) return fail(c, MCO_E_INVALID_ARG, "sub must be 1..64");
+    if (!isfinite(beta)) return fail(c, MCO_E_INVALID_ARG, "angle must be finite");
+    int rc = ready(c, 1);
+    if (rc) return rc;
+    proj_t P;
+    proj_setup(c, beta, &P);
+    const mco_geometry *g = &c->g;
+    /* per bin: draw probability times eta, and mu per unit density per material */
+    double *wk = (double *)malloc((size_t)c->n_bins * sizeof(double));
+    float *mk = (float *)malloc((size_t)c->n_bins * c->n_mat * sizeof(float));
+    if (!wk || !mk) { free(wk); free(mk); return fail(c, MCO_E_OOM, "bin tables"); }
+    for (int k = 0; k < c->n_bins; ++k) {
+        const uint64_t lo = k ? c->thr[k - 1] : 0;
+        wk[k] = (double)(c->thr[k] - lo) / 4294967296.0 *
+                (double)lerp_tab(c->t_eta, c->J, c->e_bin[k]);
+        mat_mu(c, c->e_bin[k], mk + (size_t)k * c->n_mat);
+    }
+    const double om_cone = TWO_PI_D * (double)P.omc;
+    const double da = (double)g->pu_mm * (double)g->pv_mm / ((double)sub * sub);
+    double lam[MAX_MAT];
+    for (int iv = 0; iv < g->nv; ++iv)
+        for (int iu = 0; iu < g->nu; ++iu) {
+            double acc = 0.0;
+            for (int b = 0; b < sub; ++b)
+                for (int a = 0; a < sub; ++a) {
+                    const double u = -(double)P.hu + ((double)iu + (a + 0.5) / sub) * g->pu_mm;
+                    const double v = -(double)P.hv + ((double)iv + (b + 0.5) / sub) * g->pv_mm;
+                    double w[3], r2 = 0.0, ax = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        w[k] = ((double)P.D[k] + u * P.eu[k] + v * P.ev[k]) - (double)P.S[k];
+                        r2 += w[k] * w[k];
+                    }
+                    const double R = sqrt(r2);
+                    float d[3];
+                    for (int k = 0; k < 3; ++k) {
+                        d[k] = (float)(w[k] / R);
+                        ax += w[k] / R * (double)P.ax[k];
+                    }
+                    ray_lambda(c, &P, d, lam);
+                    double e_sum = 0.0;
+                    for (int k = 0; k < c->n_bins; ++k) {
+                        double tau = 0.0;
+                        for (int m = 0; m < c->n_mat; ++m)
+                            tau += lam[m] * (double)mk[(size_t)k * c->n_mat + m];
+                        e_sum += wk[k] * exp(-tau);
+                    }
+                    acc += e_sum * (ax * da / r2);
+                }
+            out[(size_t)iv * g->nu + iu] = acc / om_cone;
+        }
+    free(wk);
+    free(mk);
+    return MCO_OK;
+}
+
+/* ------------------------------------------------------------ angular interpolation
+ * Section II-C-3: of a scan's projections only every other one's scatter is
+ * simulated; the ones between are the linear interpolation of their two
+ * neighbours in angle.  sim[n_sim][n_pix] are the simulated maps at angles
+ * beta_0, beta_2, ... of a full circle; full[2 n_sim][n_pix] receives them at
+ * the even positions and, at odd position 2i+1, 0.5 (sim[i] + sim[i+1]) with
+ * sim[n_sim] = sim[0] (the circle closes), in fp32. */
+int mco_interp_angles(const float *sim, int n_sim, int64_t n_pix, float *full) {
+    if (!sim || !full || n_sim < 1 || n_pix < 1) return MCO_E_INVALID_ARG;
+    for (int i = 0; i < n_sim; ++i) {
+        const float *a = sim + (size_t)i * n_pix;
+        const float *b = sim + (size_t)((i + 1) % n_sim) * n_pix;
+        float *e = full + (size_t)(2 * i) * n_pix, *o = e + n_pix;
+        for (int64_t p = 0; p < n_pix; ++p) {
+            e[p] = a[p];
+            o[p] = 0.5f * (a[p] + b[p]);
+        }
+    }
+    return MCO_OK;
+}

@@ -192,6 +192,17 @@ int mco_pd_score_event(mco_ctx *ctx, float angle_rad, uint64_t seed, uint64_t pi
                        int n_prior, const float o[3], const float d[3], float e_kev,
                        int material, int process, int64_t *scatter);
 
+/* Eq. (7) as the expectation of the primary image: out[nv*nu] (fp64) the
+ * expected primary tally in keV per photon emitted into the cone, each pixel
+ * integrated over sub x sub sub-pixel rays (1 .. 64) marched with the
+ * transport's step rule. */
+int mco_primary_expected(mco_ctx *ctx, float angle_rad, int sub, double *out);
+
+/* Angular interpolation of scatter maps (section II-C-3): sim[n_sim][n_pix]
+ * simulated at every other angle of a circle -> full[2 n_sim][n_pix], odd
+ * entries the mean of their two neighbours (the last wraps to the first). */
+int mco_interp_angles(const float *sim, int n_sim, int64_t n_pix, float *full);
+
 /* Which reading of the fixed-step march the transport follows. */
 int mco_set_reading(mco_ctx *ctx, int reading);
 

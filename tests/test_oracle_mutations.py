@@ -79,6 +79,15 @@ CASES = [
      "test_oracle_pd.py::test_pd_pdf_rayleigh"),
     ("pd_attenuation", "x0 * exp(-tau)", "x0 * exp(-0.5 * tau)",
      "test_oracle_pd.py::test_pd_single_scatter_brute_force"),
+    # the deterministic primary of eq. (7) and the angular interpolation
+    ("primary_cos_gamma", "acc += e_sum * (ax * da / r2);", "acc += e_sum * (da / r2);",
+     "test_oracle_primary.py::test_primary_vacuum_solid_angles"),
+    ("primary_midpoint", "((double)iu + (a + 0.5) / sub)", "((double)iu + (a + 0.0) / sub)",
+     "test_oracle_primary.py::test_primary_vacuum_solid_angles"),
+    ("primary_last_step", "(double)dl : (double)(L - a0);", "(double)dl : (double)dl;",
+     "test_oracle_primary.py::test_primary_beer_lambert_box"),
+    ("interp_neighbour", "o[p] = 0.5f * (a[p] + b[p]);", "o[p] = 0.5f * (a[p] + a[p]);",
+     "test_oracle_primary.py::test_interp_angles_closed_form"),
 ]
 
 
