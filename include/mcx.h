@@ -202,6 +202,27 @@ typedef struct mc_job {
 mc_status mc_project_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t *d_out,
                            uint64_t out_elems, uint32_t flags, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mc_project_batch
+ * without MC_BATCH_GRAPH, with the same arguments and results (each job's
+ * images bitwise those of mc_project_async), whose job, grid and photon-
+ * counter tables live in a fixed device array of the library instead of a
+ * context buffer.  It calls no hipMalloc or hipFree and no allocating
+ * library routine; the caller provides d_out.  Limits: n_jobs <=
+ * MC_STATIC_MAX_JOBS and at most MC_STATIC_MAX_PHANTOMS objects in the
+ * context (else MC_E_INVALID_ARG).  The device tables (cross sections) must
+ * already fit their buffer: after a change of spectrum, materials or response
+ * that needs a larger one, run any other projection once first (else
+ * MC_E_STATE).  Every call on one GPU shares that GPU's array (about 130 KiB,
+ * held until the process ends): calls that overlap on one GPU, from any
+ * context or stream, race and give wrong images; order them on one stream or
+ * synchronise between them.  The clear of d_out and of the counters is a
+ * kernel, not a memset. */
+#define MC_STATIC_MAX_JOBS 1024
+#define MC_STATIC_MAX_PHANTOMS 64
+mc_status mc_project_batch_static(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                                  uint64_t out_elems, void *stream);
+
 /* March probe (a measuring instrument, not part of the method): n_rays
  * straight rays with the birth directions of photons 0 .. n_rays-1 of `seed`
  * are marched through the loaded object with the transport's fixed-step rule

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -166,6 +167,8 @@ struct mc_ctx {
 
 namespace {
 
+mc_status lookup_scratch(mc_ctx *c);
+
 mc_status fail(mc_ctx *c, mc_status code, const char *fmt, ...) {
     if (c) {
         va_list ap;
@@ -211,7 +214,7 @@ mc_status use_device(mc_ctx *c) {
 
 // Regenerate host tables and upload them (synchronises the device first so
 // no queued kernel still reads the old blob).
-mc_status refresh_tables(mc_ctx *c) {
+mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     if (!c->tables_dirty) return MC_OK;
     ++c->generation;
     const int n_mat = (int)c->mats.size();
@@ -245,6 +248,9 @@ mc_status refresh_tables(mc_ctx *c) {
     put(c->eta.data(), (size_t)J * 4);
     put(c->e_bin.data(), nb * 4);
     put(guide, sizeof guide);
+    if (bytes > c->d_tables_bytes && !may_alloc)
+        return fail(c, MC_E_STATE,
+                    "the tables need a larger device buffer: run any projection once first");
     HIP_TRY(c, hipDeviceSynchronize());
     if (bytes > c->d_tables_bytes) {
         if (c->d_tables) (void)hipFree(c->d_tables);
@@ -445,6 +451,11 @@ mc_status mc_create(mc_ctx **out, int device) {
         return rc;
     }
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    rc = lookup_scratch(c);
+    if (rc) {
+        mc_destroy(c);
+        return rc;
+    }
     *out = c;
     return MC_OK;
 }
@@ -648,6 +659,132 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     return MC_OK;
 }
 
+// A batch's host-side preparation, shared by the allocating and the
+// allocation-free entry points: validation, tables, and the device tables'
+// contents (grids for every phantom, then jobs; per-job counters follow them
+// on the device and are cleared by the launch's clear kernel).
+struct BatchPlan {
+    std::vector<unsigned char> host;   // grids | jobs
+    size_t gb = 0, jbytes = 0, bytes = 0;
+    int max_lane_pal = 0;
+    uint64_t total = 0;
+    ProjFrame F0{};
+};
+
+mc_status plan_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                     uint64_t out_elems, bool may_alloc, BatchPlan &b) {
+    if (!jobs || n_jobs < 1 || n_jobs > 65536 || !d_out)
+        return fail(c, MC_E_INVALID_ARG, "need 1..65536 jobs and an output buffer");
+    if (!c->have_geom || !c->have_spec) return fail(c, MC_E_STATE, "geometry and spectrum must be set");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    const uint64_t np = (uint64_t)c->g.nu * c->g.nv, ns = (uint64_t)c->g.snu * c->g.snv;
+    uint64_t n_max = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const mc_job &jb = jobs[j];
+        if (jb.phantom < 0 || jb.phantom >= (int)c->phantoms.size() || !c->phantoms[jb.phantom].loaded)
+            return fail(c, MC_E_INVALID_ARG, "job %d: unknown phantom %d", j, jb.phantom);
+        if (!std::isfinite(jb.angle_rad)) return fail(c, MC_E_INVALID_ARG, "job %d: bad angle", j);
+        if (jb.primary_offset > out_elems || out_elems - jb.primary_offset < np ||
+            jb.scatter_offset > out_elems || out_elems - jb.scatter_offset < ns)
+            return fail(c, MC_E_INVALID_ARG, "job %d: images outside the output buffer", j);
+        rc = check_phantom(c, c->phantoms[jb.phantom]);
+        if (rc) return rc;
+        n_max = std::max(n_max, jb.n_photons);
+        b.total += jb.n_photons;
+    }
+    rc = refresh_tables(c, may_alloc);
+    if (rc) return rc;
+    rc = check_overflow(c, n_max);
+    if (rc) return rc;
+    const int n_grid = (int)c->phantoms.size();
+    b.gb = ((n_grid * sizeof(VoxelGrid) + 255) / 256) * 256;
+    b.jbytes = ((n_jobs * sizeof(JobDesc) + 255) / 256) * 256;
+    b.bytes = b.gb + b.jbytes + (size_t)n_jobs * 8;
+    b.host.assign(b.gb + b.jbytes, 0);
+    VoxelGrid *hg = (VoxelGrid *)b.host.data();
+    for (int i = 0; i < n_grid; ++i) {
+        if (!c->phantoms[i].loaded) continue;
+        hg[i] = grid_of(c, c->phantoms[i]);
+        if (hg[i].layout == kPaletteLane) b.max_lane_pal = std::max(b.max_lane_pal, hg[i].n_pal);
+    }
+    JobDesc *hj = (JobDesc *)(b.host.data() + b.gb);
+    for (int j = 0; j < n_jobs; ++j) {
+        const mc_job &jb = jobs[j];
+        hj[j].F = frame_of(c->g, jb.angle_rad);
+        hj[j].key0 = (uint32_t)jb.seed;
+        hj[j].key1 = (uint32_t)(jb.seed >> 32);
+        hj[j].n = jb.n_photons;
+        hj[j].prim = (unsigned long long *)(d_out + jb.primary_offset);
+        hj[j].scat = (unsigned long long *)(d_out + jb.scatter_offset);
+        hj[j].grid = jb.phantom;
+    }
+    b.F0 = hj[0].F;
+    return MC_OK;
+}
+
+// Kernel parameters and launch shape of a planned batch whose device tables
+// start at db.
+void batch_params(mc_ctx *c, const BatchPlan &b, unsigned char *db, int n_jobs, KParams &p,
+                  int &grid, int &block, bool &stats) {
+    common_params(c, p);
+    p.grids = (const VoxelGrid *)db;
+    p.jobs = (const JobDesc *)(db + b.gb);
+    p.job_counters = (unsigned long long *)(db + b.gb + b.jbytes);
+    p.n_jobs = n_jobs;
+    p.F = b.F0;
+    if (c->event_batch <= 0) p.event_batch = kDefaultBatchEventBatch;
+    stats = c->stats_on;
+    if (!stats) p.stats = nullptr;
+    block = c->block > 0 ? c->block : 256;
+    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
+                                         : batch_blocks_per_cu(p, b.max_lane_pal, block, stats);
+    grid = (int)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, (b.total + block - 1) / block));
+}
+
+}  // namespace
+
+// ---- scratch of the allocation-free batch entry point -------------------------
+// The device tables of mc_project_batch_static (grids, jobs, per-job photon
+// counters) live in this file-scope array: one copy per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel or a copy
+// (on the host it is only a stand-in symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device when a context is created on it.
+namespace {
+constexpr size_t kStaticGridBytes =
+    ((MC_STATIC_MAX_PHANTOMS * sizeof(VoxelGrid) + 255) / 256) * 256;
+constexpr size_t kStaticJobBytes = ((MC_STATIC_MAX_JOBS * sizeof(JobDesc) + 255) / 256) * 256;
+constexpr size_t kStaticBytes = kStaticGridBytes + kStaticJobBytes + MC_STATIC_MAX_JOBS * 8;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+unsigned char *g_scratch[kMaxDevices];   // device address of `scratch`, per device
+std::mutex g_scratch_mu;
+
+// once per device, with that device current
+mc_status lookup_scratch(mc_ctx *c) {
+    if (c->device < 0 || c->device >= kMaxDevices) return MC_OK;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[c->device]) return MC_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch[c->device] = (unsigned char *)ptr;
+    return MC_OK;
+}
+
+mc_status static_scratch(mc_ctx *c, unsigned char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device < 0 || c->device >= kMaxDevices || !g_scratch[c->device])
+        return fail(c, MC_E_STATE, "no scratch address for device %d", c->device);
+    *out = g_scratch[c->device];
+    return MC_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -873,94 +1010,35 @@ mc_status mc_project(mc_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *
 mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d_out,
                            uint64_t out_elems, uint32_t flags, void *stream) {
     if (!c) return MC_E_INVALID_ARG;
-    if (!jobs || n_jobs < 1 || n_jobs > 65536 || !d_out)
-        return fail(c, MC_E_INVALID_ARG, "need 1..65536 jobs and an output buffer");
     if (flags & ~MC_BATCH_GRAPH) return fail(c, MC_E_INVALID_ARG, "unknown batch flags");
-    if (!c->have_geom || !c->have_spec) return fail(c, MC_E_STATE, "geometry and spectrum must be set");
-    mc_status rc = use_device(c);
+    BatchPlan b;
+    mc_status rc = plan_batch(c, jobs, n_jobs, d_out, out_elems, true, b);
     if (rc) return rc;
-    const uint64_t np = (uint64_t)c->g.nu * c->g.nv, ns = (uint64_t)c->g.snu * c->g.snv;
-    uint64_t n_max = 0;
-    for (int j = 0; j < n_jobs; ++j) {
-        const mc_job &jb = jobs[j];
-        if (jb.phantom < 0 || jb.phantom >= (int)c->phantoms.size() || !c->phantoms[jb.phantom].loaded)
-            return fail(c, MC_E_INVALID_ARG, "job %d: unknown phantom %d", j, jb.phantom);
-        if (!std::isfinite(jb.angle_rad)) return fail(c, MC_E_INVALID_ARG, "job %d: bad angle", j);
-        if (jb.primary_offset > out_elems || out_elems - jb.primary_offset < np ||
-            jb.scatter_offset > out_elems || out_elems - jb.scatter_offset < ns)
-            return fail(c, MC_E_INVALID_ARG, "job %d: images outside the output buffer", j);
-        rc = check_phantom(c, c->phantoms[jb.phantom]);
-        if (rc) return rc;
-        n_max = std::max(n_max, jb.n_photons);
-    }
-    rc = refresh_tables(c);
-    if (rc) return rc;
-    rc = check_overflow(c, n_max);
-    if (rc) return rc;
-
-    // device tables: grids for every phantom, then jobs, then per-job counters
-    const int n_grid = (int)c->phantoms.size();
-    const size_t gb = ((n_grid * sizeof(VoxelGrid) + 255) / 256) * 256;
-    const size_t jbytes = ((n_jobs * sizeof(JobDesc) + 255) / 256) * 256;
-    const size_t bytes = gb + jbytes + (size_t)n_jobs * 8;
     hipStream_t s = (hipStream_t)stream;
-    if (bytes > c->d_batch_bytes) {
+    if (b.bytes > c->d_batch_bytes) {
         HIP_TRY(c, hipDeviceSynchronize());
         if (c->d_batch) (void)hipFree(c->d_batch);
         c->d_batch = nullptr;
         c->d_batch_bytes = 0;
-        HIP_TRY(c, hipMalloc(&c->d_batch, bytes));
-        c->d_batch_bytes = bytes;
+        HIP_TRY(c, hipMalloc(&c->d_batch, b.bytes));
+        c->d_batch_bytes = b.bytes;
         ++c->generation;
-    }
-    std::vector<unsigned char> host(gb + jbytes, 0);
-    VoxelGrid *hg = (VoxelGrid *)host.data();
-    int max_lane_pal = 0;
-    for (int i = 0; i < n_grid; ++i) {
-        if (!c->phantoms[i].loaded) continue;
-        hg[i] = grid_of(c, c->phantoms[i]);
-        if (hg[i].layout == kPaletteLane) max_lane_pal = std::max(max_lane_pal, hg[i].n_pal);
-    }
-    JobDesc *hj = (JobDesc *)(host.data() + gb);
-    for (int j = 0; j < n_jobs; ++j) {
-        const mc_job &jb = jobs[j];
-        hj[j].F = frame_of(c->g, jb.angle_rad);
-        hj[j].key0 = (uint32_t)jb.seed;
-        hj[j].key1 = (uint32_t)(jb.seed >> 32);
-        hj[j].n = jb.n_photons;
-        hj[j].prim = (unsigned long long *)(d_out + jb.primary_offset);
-        hj[j].scat = (unsigned long long *)(d_out + jb.scatter_offset);
-        hj[j].grid = jb.phantom;
     }
     unsigned char *db = (unsigned char *)c->d_batch;
     if (!c->batch_done)
         HIP_TRY(c, hipEventCreateWithFlags(&c->batch_done, hipEventDisableTiming));
     else
         HIP_TRY(c, hipStreamWaitEvent(s, c->batch_done, 0));
-    HIP_TRY(c, hipMemcpyAsync(db, host.data(), gb + jbytes, hipMemcpyHostToDevice, s));
-
+    HIP_TRY(c, hipMemcpyAsync(db, b.host.data(), b.host.size(), hipMemcpyHostToDevice, s));
     KParams p;
-    common_params(c, p);
-    p.grids = (const VoxelGrid *)db;
-    p.jobs = (const JobDesc *)(db + gb);
-    p.job_counters = (unsigned long long *)(db + gb + jbytes);
-    p.n_jobs = n_jobs;
-    p.F = hj[0].F;
-    if (c->event_batch <= 0) p.event_batch = kDefaultBatchEventBatch;
-    const bool stats = c->stats_on;
-    if (!stats) p.stats = nullptr;
-    const int block = c->block > 0 ? c->block : 256;
-    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
-                                         : batch_blocks_per_cu(p, max_lane_pal, block, stats);
-    uint64_t total = 0;
-    for (int j = 0; j < n_jobs; ++j) total += jobs[j].n_photons;
-    const int grid = (int)std::max<uint64_t>(
-        1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, (total + block - 1) / block));
+    int grid, block;
+    bool stats;
+    batch_params(c, b, db, n_jobs, p, grid, block, stats);
 
     if (!(flags & MC_BATCH_GRAPH)) {
         hipError_t e = launch_clear((unsigned long long *)d_out, out_elems, p.job_counters,
                                     (size_t)n_jobs, s);
-        if (e == hipSuccess) e = launch_batch(p, max_lane_pal, grid, block, stats, s);
+        if (e == hipSuccess) e = launch_batch(p, b.max_lane_pal, grid, block, stats, s);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
         HIP_TRY(c, hipEventRecord(c->batch_done, s));
         return MC_OK;
@@ -971,7 +1049,7 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
     std::memcpy(key.data(), &p, sizeof p);
     // the captured clear kernel writes through d_out, so the buffer is part of the key
     const uint64_t extra[5] = {out_elems, (uint64_t)grid, (uint64_t)block,
-                               ((uint64_t)c->generation << 8) | (uint64_t)max_lane_pal,
+                               ((uint64_t)c->generation << 8) | (uint64_t)b.max_lane_pal,
                                (uint64_t)(uintptr_t)d_out};
     std::memcpy(key.data() + sizeof p, extra, sizeof extra);
     if (!c->graph_exec || key != c->graph_key) {
@@ -984,7 +1062,7 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
         HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_clear((unsigned long long *)d_out, out_elems, p.job_counters,
                                     (size_t)n_jobs, c->stream);
-        if (e == hipSuccess) e = launch_batch(p, max_lane_pal, grid, block, stats, c->stream);
+        if (e == hipSuccess) e = launch_batch(p, b.max_lane_pal, grid, block, stats, c->stream);
         hipGraph_t gr = nullptr;
         const hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -997,6 +1075,34 @@ mc_status mc_project_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d
     }
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
     HIP_TRY(c, hipEventRecord(c->batch_done, s));
+    return MC_OK;
+}
+
+mc_status mc_project_batch_static(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                                  uint64_t out_elems, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (n_jobs > MC_STATIC_MAX_JOBS)
+        return fail(c, MC_E_INVALID_ARG, "at most %d jobs without allocation (got %d)",
+                    MC_STATIC_MAX_JOBS, n_jobs);
+    if ((int)c->phantoms.size() > MC_STATIC_MAX_PHANTOMS)
+        return fail(c, MC_E_INVALID_ARG, "at most %d phantoms without allocation (context has %d)",
+                    MC_STATIC_MAX_PHANTOMS, (int)c->phantoms.size());
+    BatchPlan b;
+    mc_status rc = plan_batch(c, jobs, n_jobs, d_out, out_elems, false, b);
+    if (rc) return rc;
+    unsigned char *db = nullptr;
+    rc = static_scratch(c, &db);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(c, hipMemcpyAsync(db, b.host.data(), b.host.size(), hipMemcpyHostToDevice, s));
+    KParams p;
+    int grid, block;
+    bool stats;
+    batch_params(c, b, db, n_jobs, p, grid, block, stats);
+    hipError_t e = launch_clear((unsigned long long *)d_out, out_elems, p.job_counters,
+                                (size_t)n_jobs, s);
+    if (e == hipSuccess) e = launch_batch(p, b.max_lane_pal, grid, block, stats, s);
+    if (e != hipSuccess) return hip_fail(c, e, "static batch launch");
     return MC_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
            "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
-           "mc_make_kramers"]
+           "mc_make_kramers", "mc_project_batch_static"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -124,6 +124,7 @@ def load():
         "mc_tally_scale": ([], C.c_double),
         "mc_phantom_add": ([P, P, P, I, I, I, F, C.POINTER(I)], I),
         "mc_project_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_uint32, P], I),
+        "mc_project_batch_static": ([P, C.POINTER(mc_job), I, P, U64, P], I),
         "mc_get_shape": ([P] + [C.POINTER(I)] * 7, I),
         "mc_tally_to_float_async": ([P, P, P, U64, C.c_double, P], I),
         "mc_savgol_async": ([P, P, P, P, I, I, I, I, P], I),
@@ -225,6 +226,21 @@ def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=N
                         j["primary_offset"], j["scatter_offset"])
     _check(ctx, load().mc_project_batch(ctx, arr, len(jobs), _dev(d_out), out_elems, flags,
                                         _stream(stream)))
+
+
+MC_STATIC_MAX_JOBS = 1024
+MC_STATIC_MAX_PHANTOMS = 64
+
+
+def mc_project_batch_static(ctx, jobs, d_out, out_elems, stream=None):
+    """mc_project_batch without device allocation (tables in the library's
+    fixed device array; calls on one GPU must not overlap)."""
+    arr = (mc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = mc_job(j["phantom"], j["angle_rad"], j["n_photons"], j["seed"],
+                        j["primary_offset"], j["scatter_offset"])
+    _check(ctx, load().mc_project_batch_static(ctx, arr, len(jobs), _dev(d_out), out_elems,
+                                               _stream(stream)))
 
 
 def mc_set_geometry(ctx, sod_mm, sdd_mm, nu, nv, pu_mm, pv_mm, step_mm, snu=None, snv=None,

@@ -209,3 +209,13 @@ def test_make_kramers_arguments(lib):
     small = np.zeros(10, np.float32)
     assert L.mc_make_kramers(150.0, 0.0, 1.0, small.ctypes.data_as(C.c_void_p),
                              small.ctypes.data_as(C.c_void_p), 10, C.byref(n)) == mcx.MC_E_INVALID_ARG
+
+
+def test_static_batch_needs_device(host_ctx):
+    import ctypes as C
+    job = (mcx.mc_job * 1)(mcx.mc_job(0, 0.0, 1, 0, 0, 0))
+    rc = mcx.load().mc_project_batch_static(host_ctx, job, 1, C.c_void_p(16), 1, None)
+    assert rc != 0
+    rc = mcx.load().mc_project_batch_static(host_ctx, job, mcx.MC_STATIC_MAX_JOBS + 1,
+                                            C.c_void_p(16), 1, None)
+    assert rc == mcx.MC_E_INVALID_ARG
