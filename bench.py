@@ -226,6 +226,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--pd-split", type=int, default=8,
+                    help="point-detector pseudo-particles per scattering (0: skip that part)")
+    ap.add_argument("--pd-rr", type=float, default=0.0, help="roulette threshold, keV")
+    ap.add_argument("--pd-fraction", type=float, default=0.1,
+                    help="point-detector photons as a fraction of the step's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to scale HBM byte counters")
@@ -237,7 +242,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2201_13191_amd import inputs, mcx
+    from paper_2201_13191_amd import inputs, mcx, metrics
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
     if args.calibrate_copy:
@@ -316,19 +321,46 @@ def main():
     p1, s1 = prim.clone(), scat.clone()
     mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"] + 1, prim, scat, stream)
     torch.cuda.synchronize()
-    a = s1.double().cpu().numpy().ravel()
-    b = scat.double().cpu().numpy().ravel()
-    d2 = float(((a - b) ** 2).sum())
-    s2 = float((a ** 2).sum() + (b ** 2).sum()) / 2.0 - d2 / 4.0
-    r = float(np.sqrt(d2 / 2.0 / s2)) if s2 > 0 else float("nan")
+    r = metrics.pair_rel_rms(s1.cpu().numpy(), scat.cpu().numpy())
     n2 = n * (r / 0.02) ** 2
     plain_2pct = {"scatter_rel_rms_at_step": r, "photons_for_2pct": n2,
                   "seconds_for_2pct": n2 / (n * args.steps / wall),
                   "method": "two independent projections (seeds s, s+1) of the step's photon "
-                            "count; r^2 = (|a-b|^2 / 2) / ((|a|^2 + |b|^2) / 2 - |a-b|^2 / 4)"}
+                            "count; r^2 = (|a-b|^2 / 2) / ((|a|^2 + |b|^2) / 2 - |a-b|^2 / 2)"}
     log(f"plain MC scatter rel-RMS {r:.4f} at {n:.3g} photons: 2 % needs {n2:.3g} photons, "
         f"{plain_2pct['seconds_for_2pct']:.2f} s")
     del p1
+
+    # the paper's scorer: point-detector scatter estimates (eq. (3)-(5)) with
+    # splitting and roulette, two seeds of a smaller photon count, timed on the
+    # launch stream; its time to a 2 % scatter map against plain MC's
+    pd = None
+    if args.pd_split > 0:
+        n_pd = max(1, int(n * args.pd_fraction))
+        g.set_estimator(mcx.MC_SCORE_POINT, args.pd_split, args.pd_rr)
+        mcx.mc_project_async(g.ctx, w["angle"], n_pd, w["seed"], prim, scat, stream)
+        torch.cuda.synchronize()
+        imgs, times = [], []
+        for sd in (w["seed"] + 2, w["seed"] + 3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            mcx.mc_project_async(g.ctx, w["angle"], n_pd, sd, prim, scat, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) * 1e-3)
+            imgs.append(scat.cpu().numpy())
+        g.set_estimator(mcx.MC_SCORE_ANALOG)
+        t_pd = float(np.mean(times))
+        r_pd = metrics.pair_rel_rms(*imgs)
+        n2_pd = n_pd * (r_pd / 0.02) ** 2
+        pd = {"split": args.pd_split, "roulette_kev": args.pd_rr, "photons": n_pd,
+              "ms_per_projection": t_pd * 1e3, "histories_per_s": n_pd / t_pd,
+              "scatter_rel_rms": r_pd, "photons_for_2pct": n2_pd,
+              "seconds_for_2pct": n2_pd * t_pd / n_pd,
+              "speedup_vs_plain_mc": plain_2pct["seconds_for_2pct"] / (n2_pd * t_pd / n_pd)}
+        log(f"point detector (split {args.pd_split}): {t_pd * 1e3:.1f} ms per {n_pd:.3g} photons, "
+            f"scatter rel-RMS {r_pd:.4f}; 2 % in {pd['seconds_for_2pct']:.3f} s "
+            f"({pd['speedup_vs_plain_mc']:.1f}x plain MC)")
 
     # march probe: the fixed-step march of straight rays alone (no physics)
     probe = None
@@ -415,6 +447,7 @@ def main():
                                  3: "generic"}[layout],
                          march_probe=probe, tally_probe=tally),
         "time_to_2pct_plain_mc": plain_2pct,
+        "time_to_2pct_point_detector": pd,
         "cpu_baseline": cpu,
         "end_to_end": {"entry": "mc_project (host images)", "ms": end_to_end_ms,
                        "histories_per_s": n / (end_to_end_ms * 1e-3)},

@@ -107,6 +107,9 @@ typedef struct mc_stats {
     uint64_t cutoff_kills, cap_hits;
     uint64_t skipped_steps;  /* steps (included in `steps`) taken as runs through
                                 uniform regions without a voxel lookup each     */
+    uint64_t pd_scores;      /* point-detector pseudo-particles scored            */
+    uint64_t pd_killed;      /* ... removed by Russian roulette                   */
+    uint64_t pd_steps;       /* march steps of their chords (included in `steps`) */
 } mc_stats;
 
 /* Create a context on HIP device `device`; allocates only small buffers.
@@ -153,6 +156,49 @@ mc_status mc_make_kramers(double kvp, double al_mm, double bin_keV, float *out_e
  * E_j = 1 + j keV, n >= 1 values (the last one repeats beyond n).  Default
  * eta(E) = E (energy integrating).  eta = 1 counts photons. */
 mc_status mc_set_detector_response(mc_ctx *ctx, const float *eta, int n);
+
+/* Scatter estimator (section II-A, eq. (3)-(5); section II-C-1).
+ * MC_SCORE_ANALOG (default): a scattered photon that crosses the panel scores
+ * eta(E) in the pixel it crosses.  MC_SCORE_POINT: the paper's point-detector
+ * estimator -- at every Compton or Rayleigh event, `split` pseudo-particles
+ * (1 .. 1024) each pick a uniform point on the panel (its random pixel) and
+ * score eta(E') p(lambda) cos(gamma) A / (2 pi R^2 split) exp(-tau): p the
+ * event's angular law per unit cosine (eq. (4) Klein-Nishina, eq. (5)
+ * Rayleigh with the form factor), lambda the cosine between the photon's
+ * direction and the direction to the point, R the distance, gamma that
+ * direction's angle to the panel normal, A the panel area, E' the energy
+ * scattered towards the point, tau the optical depth at E' from the event to
+ * the object's exit, marched with the transport's step rule.  Scores below
+ * rr_kev (keV; 0 turns roulette off) survive with probability score / rr_kev
+ * and then score rr_kev.  The scatter image has the analog image's
+ * expectation with lower variance; the primary image and every photon's
+ * history are unchanged (pseudo-particles draw from their own Philox
+ * counters).  Applies to mc_project, mc_project_async and
+ * mc_project_range_async; mc_project_batch needs MC_SCORE_ANALOG (else
+ * MC_E_STATE).  Invalid mode, split or threshold: MC_E_INVALID_ARG. */
+#define MC_SCORE_ANALOG 0
+#define MC_SCORE_POINT 1
+mc_status mc_set_estimator(mc_ctx *ctx, int mode, int split, double rr_kev);
+
+/* Eq. (7), the primary image without Monte Carlo: d_out[nv*nu] (device fp32)
+ * receives the expected primary tally per photon emitted into the cone, in
+ * keV (the analog primary image of n photons has expectation n * 2^20 times
+ * this in Q43.20 units).  Each pixel is integrated over sub x sub sub-pixel
+ * rays from the source (1 .. 64; midpoint rule, d(Omega) = cos(gamma) dA / R^2
+ * over the source cone's solid angle), each ray marched with the transport's
+ * fixed-step rule; the spectrum enters as the sampler's bin probabilities
+ * times eta(E), attenuation as exp(-sum_m mu_m(E) / rho * (rho * length)_m).
+ * The paper's 1/d^2 is this solid angle (its pixel area and obliquity left
+ * out).  Stream-ordered; one thread per pixel. */
+mc_status mc_primary_expected_async(mc_ctx *ctx, float angle_rad, int sub, float *d_out,
+                                    void *stream);
+
+/* Section II-C-3's inter-projection interpolation: scatter maps simulated at
+ * every other angle of a full circle, d_sim[n_sim][n_pix] (device fp32) ->
+ * d_full[2 n_sim][n_pix]: entry 2i is map i, entry 2i+1 the mean of maps i
+ * and i+1 (map n_sim is map 0).  Stream-ordered. */
+mc_status mc_interp_angles_async(mc_ctx *ctx, const float *d_sim, int n_sim, uint64_t n_pix,
+                                 float *d_full, void *stream);
 
 /* One projection, blocking: simulates photons 0 .. n_photons-1 (emitted into
  * the cone circumscribing the panel) with Philox key `seed`, and writes the
@@ -302,13 +348,21 @@ mc_status mc_set_layout(mc_ctx *ctx, int layout);
  * (0 for GENERIC). */
 mc_status mc_get_layout(mc_ctx *ctx, int *layout, int *palette_size);
 
-/* Launch shape of the transport kernel (0 = automatic): threads per block
- * (64, 128, 192 or 256), resident blocks per compute unit, and the event
- * batch: how many of a wave's 64 lanes must be waiting for an interaction or
- * a panel crossing before the wave stops marching and handles them (1 .. 64;
- * automatic: 58 for single projections, 54 for mc_project_batch).
- * Results never depend on these. */
+/* Launch shape of the transport kernel for single projections (0 =
+ * automatic): threads per block (64, 128, 192 or 256), resident blocks per
+ * compute unit, and the event batch: how many of a wave's 64 lanes must be
+ * waiting for an interaction or a panel crossing before the wave stops
+ * marching and handles them (1 .. 64; automatic: 58).  Results never depend
+ * on these. */
 mc_status mc_set_launch(mc_ctx *ctx, int block, int blocks_per_cu, int event_batch);
+/* The same for mc_project_batch and mc_project_batch_static (automatic: 256
+ * threads, blocks per CU from the occupancy, event batch 54).  The grid size
+ * (blocks per CU x compute units) sets the photons each thread takes. */
+mc_status mc_set_batch_launch(mc_ctx *ctx, int block, int blocks_per_cu, int event_batch);
+/* Objects of the context (mc_load_phantom and mc_phantom_add), their total
+ * voxel count and the largest palette (256 for objects stored with material
+ * ids and densities). */
+mc_status mc_get_batch_info(mc_ctx *ctx, int *n_phantoms, uint64_t *voxels, int *max_palette);
 
 /* Dimensions of the loaded object (handle 0) and of the panel and scatter grid. */
 mc_status mc_get_shape(mc_ctx *ctx, int *nx, int *ny, int *nz, int *nu, int *nv, int *snu,
@@ -340,6 +394,18 @@ typedef struct mc_tuning {
  * applied and nothing is timed.  Uses the GPU. */
 mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t seed,
                       const char *cache_path, mc_tuning *out);
+
+/* The autotuner for batches (section III's many projections of one scan, and
+ * objects of uneven size): times block size x blocks per CU (the grid size,
+ * i.e. photons per thread) x event batch x attenuation-table layout on the
+ * caller's job table with mc_project_batch (d_out: device int64[out_elems],
+ * overwritten), checks that every candidate reproduces the first one's whole
+ * output bitwise (rejecting any that does not), applies the fastest with
+ * mc_set_batch_launch and mc_set_layout, and appends it to cache_path (may be
+ * NULL) keyed by device, job count, total voxels, panel size and palette
+ * class; a cached entry is applied without timing.  Uses the GPU. */
+mc_status mc_autotune_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t *d_out,
+                            uint64_t out_elems, const char *cache_path, mc_tuning *out);
 
 /* ---- post-processing of scatter images (section II-C-3 and II-C-4) ----
  * Stream-ordered kernels on device float images [ny][nx]. */

@@ -12,14 +12,18 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libmcx.so")
+BUILD = os.environ.get("MCX_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("MCX_LIB_OUT", os.path.join(HERE, "libmcx.so"))
 ARCH = os.environ.get("MCX_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
              "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
+
+# build-time knobs, e.g. MCX_DEFINES="MCX_PREFETCH=12 MCX_EDGE_PAD=13" (steps per
+# prefetch group; edge copies past the high faces, at least the group plus one)
+HIP_FLAGS += [f"-D{d}" for d in os.environ.get("MCX_DEFINES", "").split()]
 
 SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
            ("probes.hip", "hip"),

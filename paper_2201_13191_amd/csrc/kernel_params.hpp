@@ -6,6 +6,8 @@
 namespace mcx {
 
 constexpr int kMaxMaterials = 16;
+constexpr int kKnTerms = 30;    // Taylor terms of sigma_KN / (pi r_e^2) below E / mc^2 = 0.1
+constexpr int kCohTerms = 41;   // power-series terms of the coherent shape below B = 0.1
 constexpr int kMaxScatterings = 1000;   // safety cap on interactions per history
 
 // Frame of one projection (fp32, computed on the host from the angle).
@@ -29,7 +31,10 @@ constexpr int kBrick = kBx * kBy * kBz;
 // that a centre up to kEdgePad - 1 voxels past a high face, or anywhere below
 // a low face (the float to unsigned conversion saturates at 0), reads the
 // voxel of the clamped centre without a clamp.
-constexpr int kEdgePad = 9;
+#ifndef MCX_EDGE_PAD
+#define MCX_EDGE_PAD 9
+#endif
+constexpr int kEdgePad = MCX_EDGE_PAD;
 // uniform-cell map: cubes of 2^kCellLog voxels per edge (4: measured faster
 // than 2, 8 or 16 on the 256^3 benchmark)
 constexpr int kCellLog = 2;
@@ -107,6 +112,13 @@ struct KParams {
     const VoxelGrid *grids;
     unsigned long long *job_counters;    // [n_jobs] next photon of each job
     int n_jobs;
+    // point-detector scoring (eq. (3)-(5)): pseudo-particles per scattering,
+    // Russian-roulette threshold (keV, 0: off), and the series of the angular
+    // laws' normalisations (Klein-Nishina kKnTerms, coherent kCohTerms)
+    int pd_split;
+    double pd_rr;
+    const double *kn_series;
+    const double *coh_series;
     // per-history records (debug kernel only)
     uint16_t *dbg_nint;
     uint32_t *dbg_steps;

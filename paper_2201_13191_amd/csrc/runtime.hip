@@ -38,6 +38,10 @@ hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int bl
 int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats);
 hipError_t launch_clear(unsigned long long *a, size_t na, unsigned long long *b, size_t nb,
                         hipStream_t stream);
+hipError_t launch_primary(const KParams &p, int sub, const double *bin_w, const float *bin_mu,
+                          int n_bins, float *out, hipStream_t stream);
+hipError_t launch_interp_angles(const float *sim, int n_sim, uint64_t n_pix, float *full,
+                                hipStream_t stream);
 hipError_t launch_savgol(const float *in, float *out, float *tmp, int nx, int ny, int window,
                          const float *coeffs, hipStream_t s);
 hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy, float alpha,
@@ -163,6 +167,15 @@ struct mc_ctx {
     size_t d_img_elems = 0;
 
     int block = 0, blocks_per_cu = 0, event_batch = 0;
+    int batch_block = 0, batch_bpc = 0, batch_event_batch = 0;   // mc_project_batch's own
+
+    // scatter estimator: analog, or point detector with splitting and roulette
+    int estimator = MC_SCORE_ANALOG;
+    int pd_split = 1;
+    double pd_rr = 0.0;
+    const double *dp_kn = nullptr, *dp_coh_series = nullptr;
+    const double *dp_bin_w = nullptr;
+    const float *dp_bin_mu = nullptr;
 };
 
 namespace {
@@ -224,11 +237,41 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     build_tables(mm.data(), n_mat, J, c->eta_user.empty() ? nullptr : c->eta_user.data(),
                  (int)c->eta_user.size(), c->pe, c->coh, c->inc, c->eta);
     c->J = J;
-    // blob: rb[n_mat] f64 | thr[n_bins] u64 | pe | coh | inc [n_mat*J] | eta[J] |
-    //       e_bin[n_bins] | guide[256] u32
+    // blob: rb[n_mat] f64 | kn[kKnTerms] f64 | coh series[kCohTerms] f64 |
+    //       thr[n_bins] u64 | pe | coh | inc [n_mat*J] | eta[J] | e_bin[n_bins] |
+    //       guide[256] u32
     const size_t nb = c->e_bin.size();
     const size_t tab = (size_t)n_mat * J;
-    const size_t bytes = n_mat * 8 + nb * 8 + (3 * tab + J + nb + 256) * 4;
+    //       | bin_w[n_bins] f64 | bin_mu[n_bins][n_mat] f32 (the deterministic primary)
+    const size_t head = (size_t)(n_mat + kKnTerms + kCohTerms) * 8;
+    const size_t body = nb * 8 + (3 * tab + J + nb + 256) * 4;
+    const size_t bins_off = ((head + body + 7) / 8) * 8;
+    const size_t bytes = bins_off + nb * 8 + nb * n_mat * 4;
+    double kn[kKnTerms], cohs[kCohTerms];
+    kn_norm_series(kn, kKnTerms);
+    coherent_series(cohs, kCohTerms);
+    // per spectrum bin: its draw probability times eta, and mu per unit density
+    // per material, with the transport's fp32 interpolation
+    auto lerp = [J](const float *t, float e) {
+        const float x = e - 1.0f;
+        int j = (int)x;
+        j = j < 0 ? 0 : (j > J - 2 ? J - 2 : j);
+        const float f = x - (float)j;
+        return t[j] + f * (t[j + 1] - t[j]);
+    };
+    std::vector<double> bin_w(nb);
+    std::vector<float> bin_mu(nb * n_mat);
+    for (size_t k = 0; k < nb; ++k) {
+        const uint64_t lo = k ? c->thr[k - 1] : 0;
+        bin_w[k] = (double)(c->thr[k] - lo) / 4294967296.0 *
+                   (double)lerp(c->eta.data(), c->e_bin[k]);
+        for (int m = 0; m < n_mat; ++m) {
+            const float *pe = c->pe.data() + (size_t)m * J, *co = c->coh.data() + (size_t)m * J,
+                        *in = c->inc.data() + (size_t)m * J;
+            bin_mu[k * n_mat + m] =
+                ((lerp(pe, c->e_bin[k]) + lerp(co, c->e_bin[k])) + lerp(in, c->e_bin[k])) * 0.1f;
+        }
+    }
     uint32_t guide[256];
     for (uint32_t i = 0, k = 0; i < 256; ++i) {
         while (c->thr[k] <= ((uint64_t)i << 24)) ++k;
@@ -241,6 +284,8 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
         off += n;
     };
     put(c->rayl_b.data(), n_mat * 8);
+    put(kn, sizeof kn);
+    put(cohs, sizeof cohs);
     put(c->thr.data(), nb * 8);
     put(c->pe.data(), tab * 4);
     put(c->coh.data(), tab * 4);
@@ -248,6 +293,9 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     put(c->eta.data(), (size_t)J * 4);
     put(c->e_bin.data(), nb * 4);
     put(guide, sizeof guide);
+    off = bins_off;
+    put(bin_w.data(), nb * 8);
+    put(bin_mu.data(), nb * n_mat * 4);
     if (bytes > c->d_tables_bytes && !may_alloc)
         return fail(c, MC_E_STATE,
                     "the tables need a larger device buffer: run any projection once first");
@@ -262,14 +310,18 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     HIP_TRY(c, hipMemcpy(c->d_tables, blob.data(), bytes, hipMemcpyHostToDevice));
     unsigned char *b = (unsigned char *)c->d_tables;
     c->dp_rb = (const double *)b;
-    c->dp_thr = (const uint64_t *)(b + n_mat * 8);
-    const float *f = (const float *)(b + n_mat * 8 + nb * 8);
+    c->dp_kn = (const double *)b + n_mat;
+    c->dp_coh_series = (const double *)b + n_mat + kKnTerms;
+    c->dp_thr = (const uint64_t *)(b + head);
+    const float *f = (const float *)(b + head + nb * 8);
     c->dp_pe = f;
     c->dp_coh = f + tab;
     c->dp_inc = f + 2 * tab;
     c->dp_eta = f + 3 * tab;
     c->dp_ebin = f + 3 * tab + J;
     c->dp_guide = (const uint32_t *)(f + 3 * tab + J + nb);
+    c->dp_bin_w = (const double *)(b + bins_off);
+    c->dp_bin_mu = (const float *)(b + bins_off + nb * 8);
     c->tables_dirty = false;
     return MC_OK;
 }
@@ -367,6 +419,10 @@ void common_params(mc_ctx *c, KParams &p) {
     p.flags = g.flags;
     p.event_batch = c->event_batch > 0 ? c->event_batch : kDefaultEventBatch;
     p.stats = c->d_ctl + kRing;
+    p.kn_series = c->dp_kn;
+    p.coh_series = c->dp_coh_series;
+    p.pd_split = 0;      // single projections turn the point detector on (prepare)
+    p.pd_rr = c->pd_rr;
 }
 
 // Every precondition of a projection of n photons; fills the kernel params.
@@ -391,6 +447,7 @@ mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t se
     p.key0 = (uint32_t)seed;
     p.key1 = (uint32_t)(seed >> 32);
     p.counter = c->d_ctl + (c->launches++ % kRing);
+    if (c->estimator == MC_SCORE_POINT) p.pd_split = c->pd_split;
     return MC_OK;
 }
 
@@ -405,6 +462,7 @@ void launch_shape(mc_ctx *c, const KParams &p, int layout, bool stats, int &grid
 
 mc_status run(mc_ctx *c, KParams &p, hipStream_t s, bool debug) {
     if (p.n == 0) return MC_OK;
+    if (debug) p.pd_split = 0;   // per-history records are the same with either estimator
     HIP_TRY(c, hipMemsetAsync(p.counter, 0, sizeof(unsigned long long), s));
     const bool stats = c->stats_on && !debug;
     const int layout = p.G.layout;
@@ -676,6 +734,8 @@ mc_status plan_batch(mc_ctx *c, const mc_job *jobs, int n_jobs, int64_t *d_out,
     if (!jobs || n_jobs < 1 || n_jobs > 65536 || !d_out)
         return fail(c, MC_E_INVALID_ARG, "need 1..65536 jobs and an output buffer");
     if (!c->have_geom || !c->have_spec) return fail(c, MC_E_STATE, "geometry and spectrum must be set");
+    if (c->estimator != MC_SCORE_ANALOG)
+        return fail(c, MC_E_STATE, "batches score analog: set MC_SCORE_ANALOG first");
     mc_status rc = use_device(c);
     if (rc) return rc;
     const uint64_t np = (uint64_t)c->g.nu * c->g.nv, ns = (uint64_t)c->g.snu * c->g.snv;
@@ -733,12 +793,12 @@ void batch_params(mc_ctx *c, const BatchPlan &b, unsigned char *db, int n_jobs, 
     p.job_counters = (unsigned long long *)(db + b.gb + b.jbytes);
     p.n_jobs = n_jobs;
     p.F = b.F0;
-    if (c->event_batch <= 0) p.event_batch = kDefaultBatchEventBatch;
+    p.event_batch = c->batch_event_batch > 0 ? c->batch_event_batch : kDefaultBatchEventBatch;
     stats = c->stats_on;
     if (!stats) p.stats = nullptr;
-    block = c->block > 0 ? c->block : 256;
-    const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
-                                         : batch_blocks_per_cu(p, b.max_lane_pal, block, stats);
+    block = c->batch_block > 0 ? c->batch_block : 256;
+    const int bpc = c->batch_bpc > 0 ? c->batch_bpc
+                                     : batch_blocks_per_cu(p, b.max_lane_pal, block, stats);
     grid = (int)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, (b.total + block - 1) / block));
 }
@@ -1220,6 +1280,50 @@ mc_status mc_get_stats(mc_ctx *c, mc_stats *out) {
     out->primary_hits = h[6]; out->scatter_hits = h[7];
     out->cutoff_kills = h[8]; out->cap_hits = h[9];
     out->skipped_steps = h[10];
+    out->pd_scores = h[11];
+    out->pd_killed = h[12];
+    out->pd_steps = h[13];
+    return MC_OK;
+}
+
+mc_status mc_primary_expected_async(mc_ctx *c, float beta, int sub, float *d_out, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_out) return fail(c, MC_E_INVALID_ARG, "null image");
+    if (sub < 1 || sub > 64) return fail(c, MC_E_INVALID_ARG, "sub must be 1..64");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    KParams p;
+    rc = prepare(c, beta, 0, 1, 0, p);
+    if (rc) return rc;
+    hipError_t e = launch_primary(p, sub, c->dp_bin_w, c->dp_bin_mu, (int)c->e_bin.size(), d_out,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "primary launch");
+    return MC_OK;
+}
+
+mc_status mc_interp_angles_async(mc_ctx *c, const float *d_sim, int n_sim, uint64_t n_pix,
+                                 float *d_full, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_sim || !d_full || n_sim < 1 || n_pix < 1)
+        return fail(c, MC_E_INVALID_ARG, "need maps, n_sim >= 1 and n_pix >= 1");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    hipError_t e = launch_interp_angles(d_sim, n_sim, n_pix, d_full, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "interpolation launch");
+    return MC_OK;
+}
+
+mc_status mc_set_estimator(mc_ctx *c, int mode, int split, double rr_kev) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (mode != MC_SCORE_ANALOG && mode != MC_SCORE_POINT)
+        return fail(c, MC_E_INVALID_ARG, "unknown estimator %d", mode);
+    if (split < 1 || split > 1024) return fail(c, MC_E_INVALID_ARG, "split must be 1..1024");
+    if (!(rr_kev >= 0.0) || !std::isfinite(rr_kev))
+        return fail(c, MC_E_INVALID_ARG, "roulette threshold must be finite and >= 0");
+    c->estimator = mode;
+    c->pd_split = split;
+    c->pd_rr = rr_kev;
+    ++c->generation;
     return MC_OK;
 }
 
@@ -1250,6 +1354,32 @@ mc_status mc_set_launch(mc_ctx *c, int block, int blocks_per_cu, int event_batch
     c->block = block;
     c->blocks_per_cu = blocks_per_cu;
     c->event_batch = event_batch;
+    return MC_OK;
+}
+
+mc_status mc_set_batch_launch(mc_ctx *c, int block, int blocks_per_cu, int event_batch) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (block != 0 && (block < 64 || block > 256 || block % 64))
+        return fail(c, MC_E_INVALID_ARG, "block must be 64, 128, 192 or 256");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64 || event_batch < 0 || event_batch > 64)
+        return fail(c, MC_E_INVALID_ARG, "bad launch shape");
+    c->batch_block = block;
+    c->batch_bpc = blocks_per_cu;
+    c->batch_event_batch = event_batch;
+    return MC_OK;
+}
+
+mc_status mc_get_batch_info(mc_ctx *c, int *n_phantoms, uint64_t *voxels, int *max_palette) {
+    if (!c || !n_phantoms || !voxels || !max_palette) return MC_E_INVALID_ARG;
+    *n_phantoms = 0;
+    *voxels = 0;
+    *max_palette = 0;
+    for (const Phantom &ph : c->phantoms) {
+        if (!ph.loaded) continue;
+        ++*n_phantoms;
+        *voxels += (uint64_t)ph.nx * ph.ny * ph.nz;
+        *max_palette = std::max(*max_palette, ph.generic ? 256 : ph.n_pal);
+    }
     return MC_OK;
 }
 

@@ -70,6 +70,30 @@ long double screening_b(long double z) {
 
 }  // namespace
 
+void kn_norm_series(double *c, int n) {
+    // K(a) = 2 [A + B + C + D] with A = 2 (1 + a)^2 / (a^2 (1 + 2a)),
+    // B = -(1 + a) ln(1 + 2a) / a^3, C = ln(1 + 2a) / (2a), D = -(1 + 3a) / (1 + 2a)^2;
+    // with 1/(1+2a) = sum g_k a^k, ln(1+2a) = sum l_k a^k, 1/(1+2a)^2 = sum h_k a^k the
+    // coefficient of a^k is 2 [2 (g_{k+2} + 2 g_{k+1} + g_k) - (l_{k+3} + l_{k+2})
+    // + l_{k+1} / 2 - h_k - 3 h_{k-1}] (the negative powers cancel).
+    auto g = [](int k) { return k < 0 ? 0.0L : std::pow(-2.0L, (long double)k); };
+    auto l = [](int k) {
+        return k < 1 ? 0.0L : ((k % 2) ? 1.0L : -1.0L) * std::pow(2.0L, (long double)k) / k;
+    };
+    auto h = [](int k) { return k < 0 ? 0.0L : (k + 1) * std::pow(-2.0L, (long double)k); };
+    for (int k = 0; k < n; ++k)
+        c[k] = (double)(2.0L * (2.0L * (g(k + 2) + 2.0L * g(k + 1) + g(k)) -
+                                (l(k + 3) + l(k + 2)) + l(k + 1) / 2.0L - h(k) - 3.0L * h(k - 1)));
+}
+
+void coherent_series(double *d, int n) {
+    for (int i = 0; i < n; ++i) {
+        const long double c3 = (long double)(i + 1) * (i + 2) * (i + 3) / 6.0L;
+        const long double t = c3 * (2.0L / (i + 1) - 4.0L / (i + 2) + 4.0L / (i + 3));
+        d[i] = (double)((i % 2 == 0) ? t : -t);
+    }
+}
+
 void attenuation_coefficients(double z_eff, double z_over_a, double e_kev, double out[3]) {
     const long double z = z_eff, e = e_kev;
     const long double electrons = kAvogadro * (long double)z_over_a;

@@ -31,6 +31,15 @@ double rayleigh_b(float z_eff);
 // cumulative weight, thr[n-1] = 2^32; the bin of draw x is the first k with x < thr[k].
 void spectrum_thresholds(const float *w, int n, std::vector<uint64_t> &thr);
 
+// Taylor coefficients c[0 .. n) of K(a) = sigma_KN / (pi r_e^2), a = E / mc^2: the
+// integral over the scattering cosine of the bracket of eq. (1) (S = 1).  Used
+// where the closed form cancels (small a).
+void kn_norm_series(double *c, int n);
+
+// Coefficients d[0 .. n) of the power series in B of the coherent shape
+// (1/V) int_0^V (1 + cos^2) (1 + b v)^-4 dv, B = b V, used below B = 0.1.
+void coherent_series(double *d, int n);
+
 // Savitzky-Golay weights (window odd <= 31, order < window): value at the
 // window centre of the least-squares polynomial, as fp32.
 void savgol_weights(int window, int order, float *w);

@@ -203,6 +203,40 @@ __device__ float sample_rayleigh(PhotonStream &s, float e, double b) {
     return cf;
 }
 
+// ------------------------------------------------------------------ point detector
+// K(a) = sigma_KN / (pi r_e^2) at a = E / mc^2: the integral over the scattering
+// cosine of the bracket of eq. (1) (S = 1), which normalises the Compton law of
+// eq. (4).  Its Taylor series below a = 0.1, where the closed form cancels.
+__device__ double kn_norm(const KParams &p, double a) {
+    if (a < 0.1) {
+        double s = p.kn_series[kKnTerms - 1];
+        for (int i = kKnTerms - 2; i >= 0; --i) s = s * a + p.kn_series[i];
+        return s;
+    }
+    const double d = 1.0 + 2.0 * a;
+    const double ln = log1p(2.0 * a);
+    const double first = (1.0 + a) / (a * a) * (2.0 * (1.0 + a) / d - ln / a);
+    return 2.0 * ((first + ln / (2.0 * a)) - (1.0 + 3.0 * a) / (d * d));
+}
+
+// (1/V) int_0^V (1 + cos^2) (1 + b v)^-4 dv at B = b V: eq. (2) with the screened
+// form factor integrated over the scattering cosine (per Z^2 and 2 pi r_e^2),
+// which normalises the Rayleigh law of eq. (5).  Power series below B = 0.1.
+__device__ double coherent_shape(const KParams &p, double B) {
+    if (B < 0.1) {
+        double s = p.coh_series[kCohTerms - 1];
+        for (int i = kCohTerms - 2; i >= 0; --i) s = s * B + p.coh_series[i];
+        return s;
+    }
+    const double r1 = 1.0 / (1.0 + B);
+    const double r2 = r1 * r1;
+    const double r3 = r2 * r1;
+    const double m0 = (1.0 - r3) / 3.0;
+    const double m1 = 1.0 / 6.0 - r2 / 2.0 + r3 / 3.0;
+    const double m2 = 1.0 / 3.0 - r1 + r2 - r3 / 3.0;
+    return 2.0 * m0 / B - 4.0 * m1 / (B * B) + 4.0 * m2 / (B * B * B);
+}
+
 // the direction rotated by polar angle (cosine ct, sine st) and azimuth
 // (cosine cp, sine sp), renormalised
 __device__ __forceinline__ void rotate_direction(float &dx, float &dy, float &dz, float ct,
@@ -289,7 +323,7 @@ __device__ __forceinline__ void cone_direction(const ProjFrame &F, PhotonStream 
 
 // ------------------------------------------------------------------ kernels
 enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim, kStScat,
-             kStCut, kStCap, kStSkipped, kStCount };
+             kStCut, kStCap, kStSkipped, kStPdScores, kStPdKilled, kStPdSteps, kStCount };
 
 // optical-depth increments on the grid of 2^-32: fp64 sums of them are exact,
 // so a run of equal increments can be added at once
@@ -385,8 +419,9 @@ __device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[
 
 // MODE: layout of the single object (ignored for batches, where each lane
 // follows the layout of its own job's object).  BATCH: run the job table.
-template <int MODE, bool BATCH, bool STATS, bool DEBUG>
+template <int MODE, bool BATCH, bool STATS, bool DEBUG, bool PD>
 __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
+    static_assert(!PD || (!BATCH && !DEBUG), "point-detector scoring: single projections only");
     // LDS: palette densities [256] | palette ids [256 bytes] (single object only) |
     // lane-private columns: mu per material [n_mat][bs] (fp32), then the
     // optical-depth increment of a full step per palette entry [n_pal][bs]
@@ -477,7 +512,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     double tau = 0.0, ts = 0.0;
     uint32_t k = 0, nsteps = 0;
     uint32_t cellw = 0;   // uniform-cell word at the centre of step k (0: none known)
-    bool stale = true;    // the LDS attenuation tables do not match the energy yet
+    float tab_e = -1.0f;  // energy of the lane's LDS attenuation tables (-1: none yet)
     // Between flights, three flight variables hold what the next flight
     // needs, without registers of their own: `last` the polar cosine of the
     // pending turn (birth: into the cone; scattering: away from the old
@@ -526,7 +561,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         turn = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) o[a] = F.S[a];
-        stale = true;     // tables are rebuilt when the first flight starts
+        tab_e = -1.0f;    // tables are rebuilt when the first flight starts
         n_int = 0;
         alive = true;
         flying = false;
@@ -537,54 +572,228 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         if (STATS) ++st[kStHist];
     };
 
-    int event = 0;   // pending: 1 interaction, 2 reaches the panel plane (left or missed the box)
+    // point-detector scoring (PD): the next pseudo-particle of the lane's
+    // scattering event (-1: none pending), its process, the flight in progress
+    // being a pseudo-particle's chord, and that pseudo-particle's unattenuated
+    // score and scatter bin
+    int pd_i = -1;
+    bool pd_rayl = false, pd_flight = false;
+    double pd_x0 = 0.0;
+    uint32_t pd_bin = 0;
+    const double pd_area = (double)((float)p.nu * p.pu) * (double)((float)p.nv * p.pv);
+
+    // the march of a new flight along `dir` from o, entering at tin and leaving
+    // at tout: voxel coordinates of the first step's nominal centre, the
+    // per-step increment, the step count and the last step's length
+    auto start_march = [&](const VoxelGrid &gr, const float dir[3], float tout)
+        __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float pin = o[a] + dir[a] * tin;
+            G[a] = (dir[a] * gr.inv_h) * p.step;
+            c0[a] = (pin - gr.lo[a]) * gr.inv_h + 0.5f * G[a];
+            q[a] = c0[a] + 0.0f * G[a];
+            ig[a] = 1.0f / G[a];
+        }
+        const float len = tout - tin;
+        nsteps = step_count(len, p.step);
+        last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
+        tau = 0.0;
+        const bool lane_pal = BATCH ? gr.layout == kPaletteLane : MODE == kPaletteLane;
+        cellw = lane_pal && gr.cells != nullptr ? cell_word(gr, q) : 0u;
+        k = 0;
+        flying = true;
+    };
+
+    // the interaction type at (material, E): 0 photoelectric (or any
+    // interaction without scattering), 1 Rayleigh, 2 Compton
+    auto interaction_type = [&]() __attribute__((always_inline)) -> int {
+        const int off = mat * p.J;
+        const float a = grid_lerp(p.pe + off, p.J, e);
+        const float b = grid_lerp(p.coh + off, p.J, e);
+        const float c = grid_lerp(p.inc + off, p.J, e);
+        const float tot = (a + b) + c;
+        const float xs = rng.u() * tot;
+        if ((p.flags & 1u) || xs < a) {
+            if (STATS) ++st[kStPhoto];
+            if (DEBUG && n_int == 0) h_first = 1;
+            return 0;
+        }
+        return xs < a + b ? 1 : 2;
+    };
+    // the photon scatters: polar angle by the process's sampler, then the
+    // azimuth's and the next flight's draws; cut-offs end the history
+    auto scatter = [&](bool rayleigh, int &end) __attribute__((always_inline)) {
+        float ct, e2;
+        if (rayleigh) {
+            ct = sample_rayleigh(rng, e, p.rayl_b[mat]);
+            e2 = e;
+            if (STATS) ++st[kStRayl];
+            if (DEBUG && n_int == 0) h_first = 2;
+        } else {
+            sample_compton(rng, e, ct, e2);
+            if (STATS) ++st[kStCompt];
+            if (DEBUG && n_int == 0) h_first = 3;
+        }
+        uint32_t w[2];
+        rng.draw(w);
+        dir_ct = ct;
+        phi_w = w[0];
+        ts = (double)w[1];
+        turn = true;
+        ++n_int;
+        if (e2 < 1.0f) {
+            if (STATS) ++st[kStCut];
+            end = 4;
+            turn = false;
+        } else if (n_int >= kMaxScatterings) {
+            if (STATS) ++st[kStCap];
+            end = 5;
+            turn = false;
+        } else {
+            e = e2;
+        }
+    };
+
+    // point detector, eq. (3)-(5): the pseudo-particle pd_i of the photon's
+    // n_int-th scattering at o (incoming direction d, energy e) picks a uniform
+    // point on the panel from its own Philox block (counter photon id, n_int,
+    // pd_i + 1; the photon's draws use counters ending in 0) and scores
+    // eta(E') p(lambda) cos(gamma) A / (2 pi R^2 split) exp(-tau), tau the
+    // optical depth at E' from o to the object's exit.  Roulette below
+    // pd_rr (section II-C-1).  Returns true when the chord's march started;
+    // false when the pseudo-particle needs none (killed, below 1 keV, or
+    // scored at once because it leaves the object without a step).
+    auto pd_score = [&](double tau_chord) __attribute__((always_inline)) {
+        const double x = pd_x0 * exp(-tau_chord);
+        const long long t = (long long)__builtin_rint(x * 1048576.0);
+        if (t != 0)
+            __hip_atomic_fetch_add(dev_rw(p.scat) + pd_bin, (unsigned long long)t,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (STATS) ++st[kStPdScores];
+    };
+    auto pd_start = [&]() __attribute__((always_inline)) -> bool {
+        const ProjFrame &F = p.F;
+        const uint4 w = philox4x32_10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32),
+                                                 (uint32_t)n_int, (uint32_t)pd_i + 1u),
+                                      p.key0, p.key1);
+        const float fu = unit_float(w.x) * (float)p.nu;
+        const float fv = unit_float(w.y) * (float)p.nv;
+        int iu = (int)fu, iv = (int)fv;
+        iu = iu > p.nu - 1 ? p.nu - 1 : iu;
+        iv = iv > p.nv - 1 ? p.nv - 1 : iv;
+        const float uu = fu * p.pu - F.hu, vv = fv * p.pv - F.hv;
+        float dq[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dq[a] = ((F.D[a] + uu * F.eu[a]) + vv * F.ev[a]) - o[a];
+        const double r2 =
+            ((double)dq[0] * dq[0] + (double)dq[1] * dq[1]) + (double)dq[2] * dq[2];
+        const double dist = sqrt(r2);
+        double lam =
+            (((double)d[0] * dq[0] + (double)d[1] * dq[1]) + (double)d[2] * dq[2]) / dist;
+        lam = lam > 1.0 ? 1.0 : (lam < -1.0 ? -1.0 : lam);
+        const double cg =
+            (((double)F.ax[0] * dq[0] + (double)F.ax[1] * dq[1]) + (double)F.ax[2] * dq[2]) /
+            dist;
+        float e2;
+        double pdf;
+        if (!pd_rayl) {
+            // eq. (4): Klein-Nishina per unit cosine, at the Compton energy
+            const double alpha = (double)e / 510.99895;
+            const double ratio = 1.0 + alpha * (1.0 - lam);
+            const double r = 1.0 / ratio;
+            e2 = (float)((double)e / ratio);
+            pdf = r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(p, alpha);
+        } else {
+            // eq. (5): (1 + lambda^2) F^2 per unit cosine, energy unchanged
+            const double t = (double)e / 12.398419843320026;
+            const double V = t * t;
+            const double b = p.rayl_b[mat];
+            const double wv = 1.0 + b * ((1.0 - lam) * 0.5 * V);
+            e2 = e;
+            pdf = (1.0 + lam * lam) / (((wv * wv) * wv) * wv) / (2.0 * coherent_shape(p, b * V));
+        }
+        if (e2 < 1.0f) return false;      // such a photon would be killed
+        const double eta = (double)grid_lerp(p.eta, p.J, e2);
+        double x0 = (((eta * pdf) * cg) * pd_area) /
+                    ((6.283185307179586 * r2) * (double)p.pd_split);
+        if (p.pd_rr > 0.0 && x0 < p.pd_rr) {
+            if ((double)unit_float(w.z) < x0 / p.pd_rr) {
+                x0 = p.pd_rr;
+            } else {
+                if (STATS) ++st[kStPdKilled];
+                return false;
+            }
+        }
+        pd_x0 = x0;
+        pd_bin = (uint32_t)((iv / p.bv) * p.snu + iu / p.bu);
+        float om[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) om[a] = (float)((double)dq[a] / dist);
+        float tout;
+        if (!box_entry(p.G, o, om, tin, tout)) {
+            pd_score(0.0);
+            return false;
+        }
+        if (tab_e != e2) {
+            refresh_mu(e2, p.G);
+            tab_e = e2;
+        }
+        start_march(p.G, om, tout);
+        ts = __builtin_inf();
+        pd_flight = true;
+        if (STATS) ++st[kStFlights];
+        return true;
+    };
+
+    // pending: 1 interaction, 2 reaches the panel plane (left or missed the box),
+    // 3 a pseudo-particle's chord left the object
+    int event = 0;
     for (;;) {
         int end = -1;
         // ---- 1. interactions of lanes whose flight ended inside the object
-        if (event == 1) {
-            event = 0;
-            const int off = mat * p.J;
-            const float a = grid_lerp(p.pe + off, p.J, e);
-            const float b = grid_lerp(p.coh + off, p.J, e);
-            const float c = grid_lerp(p.inc + off, p.J, e);
-            const float tot = (a + b) + c;
-            const float xs = rng.u() * tot;
-            if ((p.flags & 1u) || xs < a) {
-                if (STATS) ++st[kStPhoto];
-                if (DEBUG && n_int == 0) h_first = 1;
-                end = 3;
-            } else {
-                float ct, e2;
-                if (xs < a + b) {
-                    ct = sample_rayleigh(rng, e, p.rayl_b[mat]);
-                    e2 = e;
-                    if (STATS) ++st[kStRayl];
-                    if (DEBUG && n_int == 0) h_first = 2;
+        if constexpr (!PD) {
+            if (event == 1) {
+                event = 0;
+                const int kind = interaction_type();
+                if (kind == 0)
+                    end = 3;
+                else
+                    scatter(kind == 1, end);
+            }
+        } else {
+            // with the point detector a scattering event first scores its
+            // pseudo-particles (each one's chord marched like a flight, with
+            // tau* infinite), and the photon scatters after the last one
+            bool do_scatter = false, rayl = false;
+            if (event == 1) {
+                event = 0;
+                const int kind = interaction_type();
+                if (kind == 0) {
+                    end = 3;
+                } else if (n_int + 1 < kMaxScatterings) {
+                    pd_i = 0;
+                    pd_rayl = kind == 1;
                 } else {
-                    sample_compton(rng, e, ct, e2);
-                    if (STATS) ++st[kStCompt];
-                    if (DEBUG && n_int == 0) h_first = 3;
-                }
-                uint32_t w[2];
-                rng.draw(w);
-                dir_ct = ct;
-                phi_w = w[0];
-                ts = (double)w[1];
-                turn = true;
-                ++n_int;
-                if (e2 < 1.0f) {
-                    if (STATS) ++st[kStCut];
-                    end = 4;
-                    turn = false;
-                } else if (n_int >= kMaxScatterings) {
-                    if (STATS) ++st[kStCap];
-                    end = 5;
-                    turn = false;
-                } else if (e2 != e) {
-                    e = e2;
-                    stale = true;
+                    do_scatter = true;      // the scattered photon is not transported
+                    rayl = kind == 1;
                 }
             }
+            if (pd_i >= 0 && !flying) {
+                if (event == 3) {
+                    event = 0;
+                    pd_flight = false;
+                    pd_score(tau);
+                    ++pd_i;
+                }
+                while (pd_i < p.pd_split && !pd_start()) ++pd_i;
+                if (pd_i >= p.pd_split) {
+                    pd_i = -1;
+                    do_scatter = true;
+                    rayl = pd_rayl;
+                }
+            }
+            if (do_scatter) scatter(rayl, end);
         }
         // ---- 2. panel crossings
         with_job(event == 2, [&](const ProjFrame &F, unsigned long long *prim,
@@ -600,10 +809,13 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                                            __HIP_MEMORY_SCOPE_AGENT);
                     end = 0;
                 } else {
-                    const int su = iu / p.bu, sv = iv / p.bv;
-                    __hip_atomic_fetch_add(dev_rw(scat) + (size_t)sv * p.snu + su,
-                                           (unsigned long long)t, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    // with the point detector the scatter image holds its scores only
+                    if (!PD) {
+                        const int su = iu / p.bu, sv = iv / p.bv;
+                        __hip_atomic_fetch_add(dev_rw(scat) + (size_t)sv * p.snu + su,
+                                               (unsigned long long)t, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     end = 1;
                 }
                 if (STATS) {
@@ -691,29 +903,12 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         with_grid(alive && !flying && event == 0, [&](const VoxelGrid &gr) __attribute__((always_inline)) {
             float tout;
             if (box_entry(gr, o, d, tin, tout)) {
-                if (stale) {
+                if (tab_e != e) {
                     refresh_mu(e, gr);
-                    stale = false;
+                    tab_e = e;
                 }
                 ts = (double)(float)(-log((double)unit_float((uint32_t)ts)));
-                // voxel coordinates of the first step's nominal centre and the
-                // per-step increment; the step count and the last step's length
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float pin = o[a] + d[a] * tin;
-                    G[a] = (d[a] * gr.inv_h) * p.step;
-                    c0[a] = (pin - gr.lo[a]) * gr.inv_h + 0.5f * G[a];
-                    q[a] = c0[a] + 0.0f * G[a];
-                    ig[a] = 1.0f / G[a];
-                }
-                const float len = tout - tin;
-                nsteps = step_count(len, p.step);
-                last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
-                tau = 0.0;
-                const bool lane_pal = BATCH ? gr.layout == kPaletteLane : MODE == kPaletteLane;
-                cellw = lane_pal && gr.cells != nullptr ? cell_word(gr, q) : 0u;
-                k = 0;
-                flying = true;
+                start_march(gr, d, tout);
                 if (STATS) ++st[kStFlights];
             } else {
                 event = 2;
@@ -806,6 +1001,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                         if (STATS) {
                             st[kStSteps] += cnt;
                             st[kStSkipped] += cnt;
+                            if (PD) st[kStPdSteps] += pd_flight ? cnt : 0u;
                         }
                         tau = tn;
                         k += cnt;
@@ -858,6 +1054,10 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             bool act = true, hit = false;
             double inc_hit = 1.0;
             uint32_t code_hit = 0;
+            // a pseudo-particle's chord takes its full steps in the loop and its
+            // last (clipped) step after it, so its optical depth is exact
+            const uint32_t full = PD && pd_flight ? rem - 1u : 0xFFFFFFFFu;
+            double inc_last = 0.0;
             // the steps in order; inc_of(u) is the optical-depth increment of
             // step u.  One copy of the loop per way of finding it, chosen once
             // per group, keeps the per-step code free of layout branches.
@@ -874,10 +1074,13 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     const bool reach = act && (tn >= ts);
                     if (DEBUG) h_steps += act && (uint32_t)u < rem ? 1u : 0u;
                     if (STATS) st[kStSteps] += act && (uint32_t)u < rem ? 1ull : 0ull;
+                    if (STATS && PD)
+                        st[kStPdSteps] += pd_flight && act && (uint32_t)u < rem ? 1ull : 0ull;
                     hit = hit || reach;
                     inc_hit = reach ? inc : inc_hit;
                     code_hit = reach ? code[u] : code_hit;
-                    const bool adv = act && !reach;
+                    if (PD) inc_last = (uint32_t)u == full ? inc : inc_last;
+                    const bool adv = act && !reach && (!PD || (uint32_t)u < full);
                     tau = adv ? tn : tau;
                     k += adv ? 1u : 0u;
                     act = adv;
@@ -902,7 +1105,17 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
                     return __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
                 });
             }
-            if (k >= nsteps) {
+            if (PD && pd_flight) {
+                if (rem <= (uint32_t)kPrefetch) {
+                    // the chord's last step was in this group: add it, clipped
+                    double r = (double)last / (double)p.step;
+                    r = r > 1.0 ? 1.0 : r;
+                    tau = tau + on_grid(inc_last * r);
+                    k = nsteps;
+                    event = 3;
+                    flying = false;
+                }
+            } else if (k >= nsteps) {
                 // the flight ended inside the group (or exactly at its end)
                 event = 2;
                 flying = false;
@@ -1091,15 +1304,22 @@ template <int MODE>
 static hipError_t launch_mode(const KParams &p, int grid, int block, bool stats, bool debug,
                               hipStream_t stream) {
     const size_t lds = transport_lds_bytes(p, MODE, block);
+    const bool pd = p.pd_split > 0;   // point-detector scoring of the scatter image
     if (debug)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, false, true>), dim3(grid), dim3(block),
-                           lds, stream, p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, false, true, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
+    else if (stats && pd)
+        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false, true>), dim3(grid),
+                           dim3(block), lds, stream, p);
+    else if (pd)
+        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false, true>), dim3(grid),
+                           dim3(block), lds, stream, p);
     else if (stats)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false>), dim3(grid), dim3(block),
-                           lds, stream, p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
     else
-        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false>), dim3(grid), dim3(block),
-                           lds, stream, p);
+        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
     return hipGetLastError();
 }
 
@@ -1115,10 +1335,10 @@ hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int bl
                         hipStream_t stream) {
     const size_t lds = batch_lds_bytes(p, max_lane_palette, block);
     if (stats)
-        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, true, false>), dim3(grid),
+        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, true, false, false>), dim3(grid),
                            dim3(block), lds, stream, p);
     else
-        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, false, false>), dim3(grid),
+        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, false, false, false>), dim3(grid),
                            dim3(block), lds, stream, p);
     return hipGetLastError();
 }
@@ -1134,6 +1354,146 @@ hipError_t launch_march_probe(const KParams &p, int layout, int grid, int block,
     else
         hipLaunchKernelGGL(march_probe_kernel<kGeneric>, dim3(grid), dim3(block), 0, stream, p,
                            sum);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ eq. (7)
+// Deterministic primary: the expected primary tally per emitted photon, one
+// thread per pixel.  The pixel is integrated over sub x sub sub-pixel rays from
+// the source (midpoint rule, d(Omega) = cos(gamma) dA / R^2 over the cone's
+// Omega = 2 pi (1 - cos(theta_max))); each ray is marched with the transport's
+// step rule (nominal step centres re-anchored every 4 steps, last step clipped)
+// and collects rho * length per material in the lane's LDS column (fp64); the
+// spectrum sum uses per bin the draw probability times eta(E) (bin_w) and mu
+// per unit density per material (bin_mu, [n_bins][n_mat]), both from the host.
+template <int MODE>
+__global__ void __launch_bounds__(128) primary_kernel(const KParams p, int sub,
+                                                      const double *bin_w, const float *bin_mu,
+                                                      int n_bins, float *out) {
+    extern __shared__ double plds[];
+    float *s_pal_rho = (float *)plds;                     // [256]
+    uint8_t *s_pal_id = (uint8_t *)(s_pal_rho + 256);     // [256]
+    double *lam = plds + 160 + threadIdx.x;               // [n_mat] with stride blockDim
+    const int bs = blockDim.x;
+    if (MODE != kGeneric) {
+        for (int i = threadIdx.x; i < p.G.n_pal; i += bs) {
+            s_pal_rho[i] = p.G.pal_rho[i];
+            s_pal_id[i] = p.G.pal_id[i];
+        }
+    }
+    __syncthreads();
+    const int pix = blockIdx.x * bs + threadIdx.x;
+    if (pix >= p.nu * p.nv) return;
+    const int iu = pix % p.nu, iv = pix / p.nu;
+    const ProjFrame &F = p.F;
+    const VoxelGrid &gr = p.G;
+    const double da = (double)p.pu * (double)p.pv / ((double)sub * sub);
+    double acc = 0.0;
+    for (int b = 0; b < sub; ++b)
+        for (int a = 0; a < sub; ++a) {
+            const double u = -(double)F.hu + ((double)iu + (a + 0.5) / sub) * p.pu;
+            const double v = -(double)F.hv + ((double)iv + (b + 0.5) / sub) * p.pv;
+            double w[3], r2 = 0.0, ax = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                w[k] = ((double)F.D[k] + u * F.eu[k] + v * F.ev[k]) - (double)F.S[k];
+                r2 += w[k] * w[k];
+            }
+            const double R = sqrt(r2);
+            float d[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                d[k] = (float)(w[k] / R);
+                ax += w[k] / R * (double)F.ax[k];
+            }
+            for (int m = 0; m < p.n_mat; ++m) lam[m * bs] = 0.0;
+            float tin, tout;
+            if (box_entry(gr, F.S, d, tin, tout)) {
+                float c0[3], G[3], q[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float pin = F.S[k] + d[k] * tin;
+                    G[k] = (d[k] * gr.inv_h) * p.step;
+                    c0[k] = (pin - gr.lo[k]) * gr.inv_h + 0.5f * G[k];
+                    q[k] = c0[k];
+                }
+                const float L = tout - tin;
+                for (uint32_t k = 0;; ++k) {
+                    const float a0 = (float)k * p.step;
+                    if (!(a0 < L)) break;
+                    if ((k & 3u) == 0u) {
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) q[t] = c0[t] + (float)k * G[t];
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) q[t] = q[t] + G[t];
+                    }
+                    const uint32_t off = brick_offset(gr, voxel_index(q[0], gr.cmax[0]),
+                                                      voxel_index(q[1], gr.cmax[1]),
+                                                      voxel_index(q[2], gr.cmax[2]));
+                    const uint32_t code = dev(gr.vox)[off];
+                    float rho;
+                    int id;
+                    if (MODE == kGeneric) {
+                        rho = dev(gr.vrho)[off];
+                        id = (int)code;
+                    } else {
+                        rho = s_pal_rho[code];
+                        id = s_pal_id[code];
+                    }
+                    const double len =
+                        (float)(k + 1u) * p.step < L ? (double)p.step : (double)(L - a0);
+                    lam[id * bs] += (double)rho * len;
+                }
+            }
+            double e_sum = 0.0;
+            for (int k = 0; k < n_bins; ++k) {
+                double tau = 0.0;
+                for (int m = 0; m < p.n_mat; ++m)
+                    tau += lam[m * bs] * (double)bin_mu[k * p.n_mat + m];
+                e_sum += bin_w[k] * exp(-tau);
+            }
+            acc += e_sum * (ax * da / r2);
+        }
+    out[pix] = (float)(acc / (6.283185307179586 * (double)F.omc));
+}
+
+hipError_t launch_primary(const KParams &p, int sub, const double *bin_w, const float *bin_mu,
+                          int n_bins, float *out, hipStream_t stream) {
+    const int block = 128;
+    const int grid = (p.nu * p.nv + block - 1) / block;
+    const size_t lds = 160 * sizeof(double) + (size_t)p.n_mat * block * sizeof(double);
+    if (p.G.layout == kGeneric)
+        hipLaunchKernelGGL(primary_kernel<kGeneric>, dim3(grid), dim3(block), lds, stream, p, sub,
+                           bin_w, bin_mu, n_bins, out);
+    else
+        hipLaunchKernelGGL(primary_kernel<kPaletteLane>, dim3(grid), dim3(block), lds, stream, p,
+                           sub, bin_w, bin_mu, n_bins, out);
+    return hipGetLastError();
+}
+
+// Angular interpolation (section II-C-3): scatter maps simulated at every
+// other angle of a circle, sim[n_sim][n_pix] -> full[2 n_sim][n_pix], the even
+// entries copied, the odd ones the mean of their two neighbours (wrapping).
+__global__ void interp_angles_kernel(const float *sim, int n_sim, uint64_t n_pix, float *full) {
+    const uint64_t n = (uint64_t)n_sim * n_pix;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const uint64_t i = t / n_pix, px = t - i * n_pix;
+        const uint64_t j = i + 1 == (uint64_t)n_sim ? 0 : i + 1;
+        const float a = sim[t], b = sim[j * n_pix + px];
+        full[(2 * i) * n_pix + px] = a;
+        full[(2 * i + 1) * n_pix + px] = 0.5f * (a + b);
+    }
+}
+
+hipError_t launch_interp_angles(const float *sim, int n_sim, uint64_t n_pix, float *full,
+                                hipStream_t stream) {
+    const uint64_t n = (uint64_t)n_sim * n_pix;
+    uint64_t grid = (n + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(interp_angles_kernel, dim3((unsigned)grid), dim3(256), 0, stream, sim,
+                       n_sim, n_pix, full);
     return hipGetLastError();
 }
 
@@ -1166,14 +1526,25 @@ hipError_t launch_sample(const KParams &p, int process, int material, float e_ke
 }
 
 template <int MODE, bool BATCH>
-static int occupancy(int block, size_t lds, bool stats) {
+static int occupancy(int block, size_t lds, bool stats, bool pd) {
     int nb = 0;
+    if constexpr (!BATCH) {
+        if (pd) {
+            if (stats)
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, transport_kernel<MODE, false, true, false, true>, block, lds);
+            else
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, transport_kernel<MODE, false, false, false, true>, block, lds);
+            return nb;
+        }
+    }
     if (stats)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, transport_kernel<MODE, BATCH, true, false>, block, lds);
+            &nb, transport_kernel<MODE, BATCH, true, false, false>, block, lds);
     else
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, transport_kernel<MODE, BATCH, false, false>, block, lds);
+            &nb, transport_kernel<MODE, BATCH, false, false, false>, block, lds);
     return nb;
 }
 
@@ -1193,15 +1564,16 @@ int march_probe_blocks_per_cu(int layout, int block) {
 
 int transport_blocks_per_cu(const KParams &p, int layout, int block, bool stats) {
     const size_t lds = transport_lds_bytes(p, layout, block);
-    int nb = layout == kPaletteLane     ? occupancy<kPaletteLane, false>(block, lds, stats)
-             : layout == kPaletteShared ? occupancy<kPaletteShared, false>(block, lds, stats)
-                                        : occupancy<kGeneric, false>(block, lds, stats);
+    const bool pd = p.pd_split > 0;
+    int nb = layout == kPaletteLane     ? occupancy<kPaletteLane, false>(block, lds, stats, pd)
+             : layout == kPaletteShared ? occupancy<kPaletteShared, false>(block, lds, stats, pd)
+                                        : occupancy<kGeneric, false>(block, lds, stats, pd);
     return nb > 0 ? nb : 1;
 }
 
 int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats) {
     const int nb = occupancy<kPaletteLane, true>(block, batch_lds_bytes(p, max_lane_palette, block),
-                                                stats);
+                                                stats, false);
     return nb > 0 ? nb : 1;
 }
 

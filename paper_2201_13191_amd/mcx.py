@@ -33,7 +33,9 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
            "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
-           "mc_make_kramers", "mc_project_batch_static"]
+           "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator",
+           "mc_set_batch_launch", "mc_get_batch_info", "mc_autotune_batch",
+           "mc_primary_expected_async", "mc_interp_angles_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -75,7 +77,8 @@ class mc_conv3x3(C.Structure):
 class mc_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "histories", "steps", "flights", "photo", "rayleigh", "compton",
-        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits", "skipped_steps")]
+        "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits", "skipped_steps",
+        "pd_scores", "pd_killed", "pd_steps")]
 
 
 class MCXError(RuntimeError):
@@ -125,6 +128,12 @@ def load():
         "mc_phantom_add": ([P, P, P, I, I, I, F, C.POINTER(I)], I),
         "mc_project_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_uint32, P], I),
         "mc_project_batch_static": ([P, C.POINTER(mc_job), I, P, U64, P], I),
+        "mc_set_estimator": ([P, I, I, C.c_double], I),
+        "mc_set_batch_launch": ([P, I, I, I], I),
+        "mc_primary_expected_async": ([P, F, I, P, P], I),
+        "mc_interp_angles_async": ([P, P, I, U64, P, P], I),
+        "mc_get_batch_info": ([P, C.POINTER(I), C.POINTER(U64), C.POINTER(I)], I),
+        "mc_autotune_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_char_p, C.POINTER(mc_tuning)], I),
         "mc_get_shape": ([P] + [C.POINTER(I)] * 7, I),
         "mc_tally_to_float_async": ([P, P, P, U64, C.c_double, P], I),
         "mc_savgol_async": ([P, P, P, P, I, I, I, I, P], I),
@@ -226,6 +235,15 @@ def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=N
                         j["primary_offset"], j["scatter_offset"])
     _check(ctx, load().mc_project_batch(ctx, arr, len(jobs), _dev(d_out), out_elems, flags,
                                         _stream(stream)))
+
+
+MC_SCORE_ANALOG, MC_SCORE_POINT = 0, 1
+
+
+def mc_set_estimator(ctx, mode, split=1, rr_kev=0.0):
+    """MC_SCORE_ANALOG, or MC_SCORE_POINT: the point-detector scatter estimator
+    with `split` pseudo-particles per scattering and roulette below rr_kev."""
+    _check(ctx, load().mc_set_estimator(ctx, mode, split, float(rr_kev)))
 
 
 MC_STATIC_MAX_JOBS = 1024
@@ -361,6 +379,40 @@ def mc_autotune(ctx, angle, n_photons, seed, cache_path=None):
     t = mc_tuning()
     path = cache_path.encode() if cache_path else None
     _check(ctx, load().mc_autotune(ctx, angle, n_photons, seed, path, C.byref(t)))
+    return {n: getattr(t, n) for n, _ in mc_tuning._fields_}
+
+
+def mc_primary_expected_async(ctx, angle, sub, d_out, stream=None):
+    """Eq. (7): expected primary keV per emitted photon into device fp32 [nv, nu]."""
+    _check(ctx, load().mc_primary_expected_async(ctx, angle, sub, _dev(d_out), _stream(stream)))
+
+
+def mc_interp_angles_async(ctx, d_sim, n_sim, n_pix, d_full, stream=None):
+    """Every-other-angle scatter maps [n_sim, n_pix] -> [2 n_sim, n_pix] (device fp32)."""
+    _check(ctx, load().mc_interp_angles_async(ctx, _dev(d_sim), n_sim, n_pix, _dev(d_full),
+                                              _stream(stream)))
+
+
+def mc_set_batch_launch(ctx, block=0, blocks_per_cu=0, event_batch=0):
+    _check(ctx, load().mc_set_batch_launch(ctx, block, blocks_per_cu, event_batch))
+
+
+def mc_get_batch_info(ctx):
+    n, v, p = C.c_int(), C.c_uint64(), C.c_int()
+    _check(ctx, load().mc_get_batch_info(ctx, C.byref(n), C.byref(v), C.byref(p)))
+    return n.value, v.value, p.value
+
+
+def mc_autotune_batch(ctx, jobs, d_out, out_elems, cache_path=None):
+    """Batch autotuner: jobs as for mc_project_batch; d_out is overwritten."""
+    arr = (mc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = mc_job(j["phantom"], j["angle_rad"], j["n_photons"], j["seed"],
+                        j["primary_offset"], j["scatter_offset"])
+    t = mc_tuning()
+    path = cache_path.encode() if cache_path else None
+    _check(ctx, load().mc_autotune_batch(ctx, arr, len(jobs), _dev(d_out), out_elems, path,
+                                         C.byref(t)))
     return {n: getattr(t, n) for n, _ in mc_tuning._fields_}
 
 
@@ -527,6 +579,9 @@ class Projector:
 
     def tables(self, n_mat):
         return mc_get_tables(self.ctx, n_mat)
+
+    def set_estimator(self, mode, split=1, rr_kev=0.0):
+        mc_set_estimator(self.ctx, mode, split, rr_kev)
 
     def set_layout(self, layout):
         mc_set_layout(self.ctx, layout)

@@ -6,6 +6,8 @@
   V_b = sum_p Var(b_p), and ((||a - b||^2 - V_b) / (||b||^2 - V_b))^(1/2)
   estimates ||a - s|| / ||s|| against the noise-free image s when a is
   independent of b (negative estimates clip to 0).
+* pair_rel_rms(a, b): the rel-RMS of either of two independent estimates of
+  equal precision against the noise-free image.
 * The paper's quantitative measures (section II-E, eq. (9)-(11)): MSE, the
   normalised cross-correlation NCC and the contrast-to-noise ratio CNR of a
   region of interest against a background region.
@@ -40,6 +42,18 @@ def debiased_rel_rms(a, batches):
     if den <= 0:
         return float("inf")
     return float(np.sqrt(max(num, 0.0) / den))
+
+
+def pair_rel_rms(a, b):
+    """rel-RMS ||a - s|| / ||s|| of one estimate against the noise-free image s,
+    from two independent estimates a, b of equal precision: E||a - b||^2 = 2V
+    and E(||a||^2 + ||b||^2) / 2 = ||s||^2 + V, so
+    r^2 = (||a - b||^2 / 2) / ((||a||^2 + ||b||^2) / 2 - ||a - b||^2 / 2)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    v = float(np.sum((a - b) ** 2)) / 2.0
+    s2 = float(np.sum(a ** 2) + np.sum(b ** 2)) / 2.0 - v
+    return float(np.sqrt(v / s2)) if s2 > 0 else float("inf")
 
 
 def mse(x1, x2):

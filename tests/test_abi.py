@@ -211,6 +211,15 @@ def test_make_kramers_arguments(lib):
                              small.ctypes.data_as(C.c_void_p), 10, C.byref(n)) == mcx.MC_E_INVALID_ARG
 
 
+def test_estimator_arguments(host_ctx):
+    mcx.mc_set_estimator(host_ctx, mcx.MC_SCORE_POINT, 8, 0.5)
+    mcx.mc_set_estimator(host_ctx, mcx.MC_SCORE_ANALOG)
+    for bad in [(2, 1, 0.0), (1, 0, 0.0), (1, 1025, 0.0), (1, 4, -1.0), (1, 4, float("inf")),
+                (1, 4, float("nan"))]:
+        with pytest.raises(mcx.MCXError):
+            mcx.mc_set_estimator(host_ctx, *bad)
+
+
 def test_static_batch_needs_device(host_ctx):
     import ctypes as C
     job = (mcx.mc_job * 1)(mcx.mc_job(0, 0.0, 1, 0, 0, 0))

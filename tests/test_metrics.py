@@ -35,3 +35,16 @@ def test_debiased_rel_rms_recovers_true_error():
     deb = M.debiased_rel_rms(a, batches)
     assert raw > 0.05                      # the raw figure is dominated by the reference's noise
     assert abs(deb - 0.02) < 0.004
+
+
+def test_pair_rel_rms_recovers_noise_level():
+    """Two independent noisy estimates of a known image: the pair estimate
+    equals the known rel-RMS of either one (Gaussian noise of known sigma)."""
+    rng = np.random.default_rng(2)
+    s = 50.0 + 10.0 * np.cos(np.linspace(0, 9, 200_000))
+    sigma = 7.0
+    a = s + rng.normal(0, sigma, s.size)
+    b = s + rng.normal(0, sigma, s.size)
+    true_r = sigma * np.sqrt(s.size) / np.linalg.norm(s)
+    assert abs(M.pair_rel_rms(a, b) / true_r - 1) < 0.01
+    assert M.pair_rel_rms(s, s) == 0.0

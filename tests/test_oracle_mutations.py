@@ -30,7 +30,8 @@ CASES = [
      "test_oracle_samplers.py::test_rayleigh_angles_chi2"),
     ("last_step_unclipped", "inc = on_grid(inc * r);", "inc = on_grid(inc);",
      "test_oracle_transport.py::test_beer_lambert_slab"),
-    ("midpoint_dropped", "* P->inv_h + 0.5f * G[a];", "* P->inv_h;",
+    ("midpoint_dropped", "* P->inv_h + 0.5f * G[a];\n    }\n    const double ts",
+     "* P->inv_h;\n    }\n    const double ts",
      "test_oracle_transport.py::test_tiny_phantom_primary_brute_force"),
     ("type_order", "if (x < pe + coh) {", "if (x < pe + inc) {",
      "test_oracle_transport.py::test_interaction_fractions"),
