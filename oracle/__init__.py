@@ -20,7 +20,7 @@ PROC_SOURCE_ENERGY, PROC_RAYLEIGH, PROC_COMPTON, PROC_SOURCE_DIR = 0, 1, 2, 3
 END_PRIMARY, END_SCATTER, END_MISSED, END_PHOTO, END_CUTOFF, END_CAP = range(6)
 FIRST_NONE, FIRST_PHOTO, FIRST_RAYLEIGH, FIRST_COMPTON = range(4)
 READING_GRID, READING_PLAIN = 0, 1
-SCORE_ANALOG, SCORE_POINT = 0, 1
+SCORE_ANALOG, SCORE_POINT, SCORE_POINT_MIXED = 0, 1, 2
 
 
 class Material(C.Structure):

@@ -127,6 +127,8 @@ typedef struct {
     uint32_t cached_blk;
     int have_blk;
     uint32_t blk[4];
+    int pseudo;           /* a pseudo-particle's stream (see rng_init_pseudo) */
+    uint32_t n, tag;
 } rng_t;
 
 static void rng_init(rng_t *r, uint64_t seed, uint64_t pid) {
@@ -135,12 +137,26 @@ static void rng_init(rng_t *r, uint64_t seed, uint64_t pid) {
     r->pid = pid;
     r->k = 0;
     r->have_blk = 0;
+    r->pseudo = 0;
+}
+
+/* The stream of pseudo-particle i of the photon's n-th scattering when it
+ * needs more than one block: counter (photon id, n, (i + 1) * 2^12 + block). */
+static void rng_init_pseudo(rng_t *r, uint64_t seed, uint64_t pid, uint32_t n, uint32_t i) {
+    rng_init(r, seed, pid);
+    r->pseudo = 1;
+    r->n = n;
+    r->tag = (i + 1u) << 12;
 }
 
 static uint32_t rng_raw(rng_t *r) {
     uint32_t b = r->k >> 2;
     if (!r->have_blk || b != r->cached_blk) {
         uint32_t ctr[4] = {(uint32_t)r->pid, (uint32_t)(r->pid >> 32), b, 0u};
+        if (r->pseudo) {
+            ctr[2] = r->n;
+            ctr[3] = r->tag | b;
+        }
         mco_philox4x32_10(ctr, r->key, r->blk);
         r->cached_blk = b;
         r->have_blk = 1;
@@ -793,6 +809,55 @@ static double pd_pdf(const mco_ctx *c, int proc, int m, float e, double lam, flo
            (2.0 * (double)coh_g((long double)(c->rayl_b[m] * V)));
 }
 
+/* The mixed estimator's Rayleigh pseudo-particle: Rayleigh laws are sharply
+ * forward peaked (the form factor), so a random point on the panel rarely
+ * lands where the law is large and the point-detector score of eq. (5) has a
+ * heavy tail.  Instead the pseudo-particle draws its direction from the
+ * Rayleigh law itself (the photon's sampler, then an azimuth, from its own
+ * stream) and, if that line crosses the panel, scores eta(E) / split times
+ * exp(-tau) to the object's exit in the pixel it crosses: the same
+ * expectation (the law's density cancels the score's p(lambda)). */
+static void pd_rayleigh_along_law(const mco_ctx *c, const proj_t *P, uint64_t seed,
+                                  uint64_t pid, int n, int i, const float o[3],
+                                  const float d[3], float e, int m, int64_t *scat,
+                                  mco_stats *st) {
+    const mco_geometry *g = &c->g;
+    rng_t r;
+    rng_init_pseudo(&r, seed, pid, (uint32_t)n, (uint32_t)i);
+    const float ct = sample_rayleigh(&r, e, c->rayl_b[m]);
+    const double phi = TWO_PI_D * (double)rng_u(&r);
+    float om[3] = {d[0], d[1], d[2]};
+    rotate(om, ct, (float)cos(phi), (float)sin(phi));
+    int iu, iv;
+    if (!panel_pixel(c, P, o, om, &iu, &iv)) return;     /* misses the panel */
+    double x0 = (double)lerp_tab(c->t_eta, c->J, e) / (double)c->split;
+    const double u_rr = (double)rng_u(&r);
+    if (c->rr_kev > 0.0 && x0 < c->rr_kev) {
+        if (u_rr < x0 / c->rr_kev) {
+            x0 = c->rr_kev;
+        } else {
+            st->pd_killed++;
+            return;
+        }
+    }
+    double tau = 0.0;
+    float tin, tout;
+    if (box_hit(P, o, om, &tin, &tout)) {
+        float mm[MAX_MAT], pint[3];
+        size_t v;
+        uint32_t steps = 0;
+        mat_mu(c, e, mm);
+        if (c->reading == MCO_READING_PLAIN)
+            (void)march_plain(c, P, o, om, tin, tout, mm, INFINITY, pint, &v, &steps, &tau);
+        else
+            (void)march(c, P, o, om, tin, tout, mm, INFINITY, pint, &v, &steps, &tau);
+        st->pd_steps += steps;
+    }
+    const int64_t L = (int64_t)llrint(x0 * exp(-tau) * 1048576.0);
+    scat[(size_t)(iv / (g->nv / g->snv)) * g->snu + (size_t)(iu / (g->nu / g->snu))] += L;
+    st->pd_scores++;
+}
+
 static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t pid, int n,
                      const float o[3], const float d[3], float e, int m, int proc,
                      int64_t *scat, mco_stats *st) {
@@ -801,6 +866,10 @@ static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t 
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     const double area = (double)((float)g->nu * g->pu_mm) * (double)((float)g->nv * g->pv_mm);
     for (int i = 0; i < c->split; ++i) {
+        if (proc == MCO_PROC_RAYLEIGH && c->estimator == MCO_SCORE_POINT_MIXED) {
+            pd_rayleigh_along_law(c, P, seed, pid, n, i, o, d, e, m, scat, st);
+            continue;
+        }
         const uint32_t ctr[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), (uint32_t)n,
                                  (uint32_t)i + 1u};
         uint32_t w[4];
@@ -920,7 +989,7 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
             if (!n_int) h->first = MCO_FIRST_COMPTON;
         }
         double phi = TWO_PI_D * (double)rng_u(&r);
-        if (c->estimator == MCO_SCORE_POINT && scat)
+        if (c->estimator != MCO_SCORE_ANALOG && scat)
             pd_event(c, P, seed, pid, n_int, p, d, e, m,
                      x < pe + coh ? MCO_PROC_RAYLEIGH : MCO_PROC_COMPTON, scat, st);
         rotate(d, ct, (float)cos(phi), (float)sin(phi));
@@ -1159,7 +1228,7 @@ double mco_tally_scale(void) { return 1.0 / 1048576.0; }
 
 int mco_set_estimator(mco_ctx *c, int mode, int split, double rr_kev) {
     if (!c) return MCO_E_INVALID_ARG;
-    if (mode != MCO_SCORE_ANALOG && mode != MCO_SCORE_POINT)
+    if (mode != MCO_SCORE_ANALOG && mode != MCO_SCORE_POINT && mode != MCO_SCORE_POINT_MIXED)
         return fail(c, MCO_E_INVALID_ARG, "unknown estimator");
     if (split < 1 || split > 1024) return fail(c, MCO_E_INVALID_ARG, "split must be 1..1024");
     if (!(rr_kev >= 0.0) || !isfinite(rr_kev))

@@ -64,8 +64,11 @@ enum {
 enum {
     MCO_SCORE_ANALOG = 0,   /* each scattered photon that crosses the panel scores
                                in the pixel it crosses */
-    MCO_SCORE_POINT = 1     /* point-detector scores of eq. (3)-(5) at every
+    MCO_SCORE_POINT = 1,    /* point-detector scores of eq. (3)-(5) at every
                                scattering, with splitting and Russian roulette */
+    MCO_SCORE_POINT_MIXED = 2  /* eq. (3)/(4) at Compton events; Rayleigh
+                                  pseudo-particles follow the Rayleigh law and
+                                  score where they cross the panel */
 };
 
 /* geometry flags */
@@ -170,12 +173,16 @@ int mco_debug_histories(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t 
 int mco_debug_paths(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t m, uint64_t seed,
                     float *x_first, int32_t *pixel, float *e_end);
 
-/* Scatter estimator: MCO_SCORE_ANALOG (default) or MCO_SCORE_POINT, the
+/* Scatter estimator: MCO_SCORE_ANALOG (default), MCO_SCORE_POINT, the
  * point-detector estimator of eq. (3)-(5) (section II-A) with `split`
  * pseudo-particles per scattering event (1..1024) and Russian roulette below
- * rr_kev (keV; 0 turns it off) (section II-C-1).  With MCO_SCORE_POINT the
- * scatter image holds the estimator's scores (same expectation as the analog
- * image); the primary image and every photon's history are unchanged. */
+ * rr_kev (keV; 0 turns it off) (section II-C-1), or MCO_SCORE_POINT_MIXED: the
+ * same at Compton events, while a Rayleigh event's pseudo-particles draw their
+ * directions from the Rayleigh law and score eta(E) / split exp(-tau) where
+ * they cross the panel (same expectation, no heavy tail from the form
+ * factor's forward peak).  With either the scatter image holds the
+ * estimator's scores (same expectation as the analog image); the primary
+ * image and every photon's history are unchanged. */
 int mco_set_estimator(mco_ctx *ctx, int mode, int split, double rr_kev);
 
 /* The point-detector scorer's angular pdf per unit scattering cosine

@@ -74,12 +74,18 @@ CASES = [
      "lerp_tab(c->t_eta, c->J, e);", "test_oracle_pd.py::test_pd_vacuum_event_integral"),
     ("pd_mu_at_incoming_energy", "mat_mu(c, e2, mm);", "mat_mu(c, e, mm);",
      "test_oracle_pd.py::test_pd_event_attenuated_integral"),
-    ("pd_roulette_weight", "x0 = c->rr_kev;", "x0 = x0 * 1.0;",
+    ("pd_roulette_weight", "uniform01(w[2]) < x0 / c->rr_kev) {\n                x0 = c->rr_kev;",
+     "uniform01(w[2]) < x0 / c->rr_kev) {\n                x0 = x0 * 1.0;",
      "test_oracle_pd.py::test_pd_matches_analog_expectation"),
     ("pd_rayleigh_norm", "(2.0 * (double)coh_g(", "(1.0 * (double)coh_g(",
      "test_oracle_pd.py::test_pd_pdf_rayleigh"),
-    ("pd_attenuation", "x0 * exp(-tau)", "x0 * exp(-0.5 * tau)",
+    ("pd_attenuation", "const double x = x0 * exp(-tau);", "const double x = x0 * exp(-0.5 * tau);",
      "test_oracle_pd.py::test_pd_single_scatter_brute_force"),
+    ("pd_mixed_rayleigh_angle", "rotate(om, ct, (float)cos(phi), (float)sin(phi));",
+     "rotate(om, -ct, (float)cos(phi), (float)sin(phi));",
+     "test_oracle_pd.py::test_pd_vacuum_event_integral"),
+    ("pd_mixed_split_norm", "lerp_tab(c->t_eta, c->J, e) / (double)c->split;",
+     "lerp_tab(c->t_eta, c->J, e);", "test_oracle_pd.py::test_pd_vacuum_event_integral"),
     # the deterministic primary of eq. (7) and the angular interpolation
     ("primary_cos_gamma", "acc += e_sum * (ax * da / r2);", "acc += e_sum * (da / r2);",
      "test_oracle_primary.py::test_primary_vacuum_solid_angles"),

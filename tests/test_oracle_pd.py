@@ -104,15 +104,17 @@ def _panel_flux(o_pt, d, e, dsig, n_q=6, geo=VAC_GEO, mu_exit=None):
     return out
 
 
-@pytest.mark.parametrize("process", ["compton", "rayleigh"])
-def test_pd_vacuum_event_integral(oracle_lib, process):
+@pytest.mark.parametrize("process,mode", [("compton", oracle.SCORE_POINT),
+                                          ("rayleigh", oracle.SCORE_POINT),
+                                          ("rayleigh", oracle.SCORE_POINT_MIXED)])
+def test_pd_vacuum_event_integral(oracle_lib, process, mode):
     ids, rho = inputs.box_phantom(8, 8, 8, 1, 0.0)
     o = oracle.Oracle()
     o.load_phantom(ids, rho, 2.0)
     o.set_geometry(**VAC_GEO)
     o.set_spectrum(*inputs.mono_spectrum(100.0))
     split = 1024
-    o.set_estimator(oracle.SCORE_POINT, split, 0.0)
+    o.set_estimator(mode, split, 0.0)
     o_pt = np.array([5.0, -3.0, 2.0], np.float32)
     d = np.array([-1.0, 0.45, 0.3])
     d = (d / np.linalg.norm(d)).astype(np.float32)
@@ -134,7 +136,8 @@ def test_pd_vacuum_event_integral(oracle_lib, process):
     zt = (tot.mean() - expect.sum()) / (tot.std(ddof=1) / np.sqrt(n_ev))
     assert abs(zt) < 5, (tot.mean(), expect.sum())
     assert abs(tot.mean() / expect.sum() - 1) < 0.01
-    assert o.stats()["pd_scores"] == n_ev * split
+    if mode == oracle.SCORE_POINT:
+        assert o.stats()["pd_scores"] == n_ev * split
 
 
 def test_pd_event_attenuated_integral(oracle_lib):
@@ -177,7 +180,8 @@ def test_pd_event_attenuated_integral(oracle_lib):
     assert abs(tot_s.mean() / expect.sum() - 1) < 0.01, (tot_s.mean(), expect.sum())
 
 
-def test_pd_single_scatter_brute_force(oracle_lib):
+@pytest.mark.parametrize("mode", [oracle.SCORE_POINT, oracle.SCORE_POINT_MIXED])
+def test_pd_single_scatter_brute_force(oracle_lib, mode):
     """Scores of every first scattering in the thin-block geometry against the
     fp64 single-scatter integral (energy per emitted photon), on 4 x 4 blocks
     of pixels: the forward peak of the Rayleigh law gives the per-pixel
@@ -191,7 +195,7 @@ def test_pd_single_scatter_brute_force(oracle_lib):
     pe, coh, inc, _ = o.tables(5)
     _, en = single_scatter_expectation(pe, coh, inc)
     split = 8
-    o.set_estimator(oracle.SCORE_POINT, split, 0.0)
+    o.set_estimator(mode, split, 0.0)
     n, seed = 400_000, 3
     n_int, _, end, first = o.debug_histories(0.0, 0, n, seed)
     x1, _, _ = o.debug_paths(0.0, 0, n, seed)
@@ -252,10 +256,12 @@ def cyl30(oracle_lib):
     return o, _batches(o, 1_000_000, range(100, 108))
 
 
-@pytest.mark.parametrize("rr", [0.0, 0.3])
-def test_pd_matches_analog_expectation(cyl30, rr):
+@pytest.mark.parametrize("mode,rr", [(oracle.SCORE_POINT, 0.0), (oracle.SCORE_POINT, 0.3),
+                                     (oracle.SCORE_POINT_MIXED, 0.0),
+                                     (oracle.SCORE_POINT_MIXED, 0.3)])
+def test_pd_matches_analog_expectation(cyl30, mode, rr):
     o, analog = cyl30
-    o.set_estimator(oracle.SCORE_POINT, 8, rr)
+    o.set_estimator(mode, 8, rr)
     o.stats()
     pd = _batches(o, 100_000, range(200, 208))
     st = o.stats()
@@ -280,11 +286,12 @@ def test_pd_matches_analog_wide_angle(oracle_lib):
     o.set_geometry(**SS_GEO)
     o.set_spectrum(*inputs.mono_spectrum(60.0))
     analog = _batches(o, 1_000_000, range(500, 508))
-    o.set_estimator(oracle.SCORE_POINT, 8, 0.0)
-    pd = _batches(o, 200_000, range(600, 608))
-    zmax, zt, ratio = _same_expectation(pd, analog)
-    assert abs(zt) < 5, (zmax, zt, ratio)
-    assert abs(ratio - 1) < 0.03, ratio
+    for mode in (oracle.SCORE_POINT, oracle.SCORE_POINT_MIXED):
+        o.set_estimator(mode, 8, 0.0)
+        pd = _batches(o, 200_000, range(600, 608))
+        zmax, zt, ratio = _same_expectation(pd, analog)
+        assert abs(zt) < 5, (mode, zmax, zt, ratio)
+        assert abs(ratio - 1) < 0.03, (mode, ratio)
 
 
 def test_pd_matches_analog_polychromatic(oracle_lib):
@@ -294,11 +301,12 @@ def test_pd_matches_analog_polychromatic(oracle_lib):
     o.set_geometry(**CYL_GEO)
     o.set_spectrum(*inputs.kramers_spectrum(120, 2.0))
     analog = _batches(o, 600_000, range(300, 308))
-    o.set_estimator(oracle.SCORE_POINT, 6, 0.0)
-    pd = _batches(o, 80_000, range(400, 408))
-    zmax, zt, ratio = _same_expectation(pd, analog)
-    assert zmax < 5 and abs(zt) < 5, (zmax, zt, ratio)
-    assert abs(ratio - 1) < 0.03, ratio
+    for mode in (oracle.SCORE_POINT, oracle.SCORE_POINT_MIXED):
+        o.set_estimator(mode, 6, 0.0)
+        pd = _batches(o, 80_000, range(400, 408))
+        zmax, zt, ratio = _same_expectation(pd, analog)
+        assert zmax < 5 and abs(zt) < 5, (mode, zmax, zt, ratio)
+        assert abs(ratio - 1) < 0.03, (mode, ratio)
 
 
 def test_pd_leaves_histories_unchanged(oracle_lib):
@@ -323,7 +331,7 @@ def test_pd_leaves_histories_unchanged(oracle_lib):
 
 def test_pd_estimator_arguments(oracle_lib):
     o = oracle.Oracle()
-    for bad in [(2, 1, 0.0), (1, 0, 0.0), (1, 1025, 0.0), (1, 4, -1.0), (1, 4, float("nan"))]:
+    for bad in [(3, 1, 0.0), (1, 0, 0.0), (1, 1025, 0.0), (1, 4, -1.0), (1, 4, float("nan"))]:
         with pytest.raises(oracle.OracleError):
             o.set_estimator(*bad)
     with pytest.raises(oracle.OracleError):
