@@ -122,3 +122,33 @@ def test_pin_catches_planted_mistake(workdir, name, orig, bad, pin):
                         os.path.join(HERE, pin)], cwd=ROOT, env=env, capture_output=True,
                        text=True, timeout=600)
     assert r.returncode == 1 and "failed" in r.stdout, (name, r.stdout[-2000:])
+
+
+RECON_CASES = [
+    # (id, original text, planted mistake, pin that must fail) in oracle/recon.py
+    ("ramp_odd_sign", "h[odd] = -1.0 /", "h[odd] = 1.0 /", "test_ramp_kernel_frequency_response"),
+    ("fdk_distance_weight", "f += (R * R) / (L * L) * val", "f += val", "test_fdk_uniform_ball"),
+    ("fdk_detector_scale", "fu = (av / s + nu * pu / 2) / pu - 0.5",
+     "fu = (av + nu * pu / 2) / pu - 0.5", "test_fdk_uniform_ball"),
+    ("eq8_sign", "- np.log(ip / (ip + np.asarray(is_, np.float64)))",
+     "+ np.log(ip / (ip + np.asarray(is_, np.float64)))", "test_eq8_recovers_primary"),
+    ("otsu_criterion", "v = w0 * w1 * (m0 - m1) ** 2", "v = w0 * (m0 - m1) ** 2",
+     "test_otsu_two_modes"),
+]
+
+
+@pytest.mark.parametrize("name,orig,bad,pin", RECON_CASES, ids=[c[0] for c in RECON_CASES])
+def test_recon_pin_catches_planted_mistake(name, orig, bad, pin):
+    import types
+    import test_oracle_recon as T
+    src = open(os.path.join(ROOT, "oracle", "recon.py")).read()
+    assert src.count(orig) == 1, f"mutation anchor not unique/present: {orig!r}"
+    mod = types.ModuleType("recon_mutant")
+    exec(compile(src.replace(orig, bad), "recon_mutant.py", "exec"), mod.__dict__)
+    saved = T.recon
+    T.recon = mod
+    try:
+        with pytest.raises(AssertionError):
+            getattr(T, pin)()
+    finally:
+        T.recon = saved
