@@ -50,15 +50,15 @@ def ramp_kernel(n, t):
     return h
 
 
-def fdk(proj, geo, vol_shape, voxel_mm):
-    """proj[n_ang][nv][nu] line integrals at b_i = 2 pi i / n_ang -> mu[nz][ny][nx]
-    (per mm), the volume centred on the origin with cubic voxels."""
+def fdk_filter(proj, geo):
+    """The FDK's weighting and filtering: proj[n_ang][nv][nu] line integrals ->
+    the filtered projections q on the virtual panel through the axis."""
     proj = np.asarray(proj, np.float64)
     n_ang, nv, nu = proj.shape
     R, D = float(geo["sod_mm"]), float(geo["sdd_mm"])
     pu, pv = float(geo["pu_mm"]), float(geo["pv_mm"])
     s = R / D
-    tu, tv = pu * s, pv * s                      # virtual-panel pitch
+    tu = pu * s                                  # virtual-panel pitch along u
     a = (-nu * pu / 2 + (np.arange(nu) + 0.5) * pu) * s
     b = (-nv * pv / 2 + (np.arange(nv) + 0.5) * pv) * s
     A, B = np.meshgrid(a, b, indexing="xy")
@@ -69,6 +69,17 @@ def fdk(proj, geo, vol_shape, voxel_mm):
         pw = proj[i] * weight
         for r in range(nv):
             q[i, r] = np.convolve(pw[r], h, mode="full")[nu - 1:2 * nu - 1] * tu
+    return q
+
+
+def fdk_backproject(q, geo, vol_shape, voxel_mm):
+    """The FDK's distance-weighted backprojection of filtered projections
+    q[n_ang][nv][nu] at b_i = 2 pi i / n_ang -> mu[nz][ny][nx]."""
+    q = np.asarray(q, np.float64)
+    n_ang, nv, nu = q.shape
+    R, D = float(geo["sod_mm"]), float(geo["sdd_mm"])
+    pu, pv = float(geo["pu_mm"]), float(geo["pv_mm"])
+    s = R / D
     nz, ny, nx = vol_shape
     xs = (np.arange(nx) + 0.5) * voxel_mm - nx * voxel_mm / 2
     ys = (np.arange(ny) + 0.5) * voxel_mm - ny * voxel_mm / 2
@@ -96,6 +107,12 @@ def fdk(proj, geo, vol_shape, voxel_mm):
                     wgt_u * wgt_v
         f += (R * R) / (L * L) * val
     return 0.5 * (2.0 * np.pi / n_ang) * f
+
+
+def fdk(proj, geo, vol_shape, voxel_mm):
+    """proj[n_ang][nv][nu] line integrals at b_i = 2 pi i / n_ang -> mu[nz][ny][nx]
+    (per mm), the volume centred on the origin with cubic voxels."""
+    return fdk_backproject(fdk_filter(proj, geo), geo, vol_shape, voxel_mm)
 
 
 def histogram(x, lo, hi, bins):
