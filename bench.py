@@ -225,10 +225,14 @@ def main():
     ap.add_argument("--photons", type=int, default=0, help="override photons per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pd-split", type=int, default=8,
                     help="point-detector pseudo-particles per scattering (0: skip that part)")
     ap.add_argument("--pd-rr", type=float, default=0.0, help="roulette threshold, keV")
+    ap.add_argument("--pd-point-only", dest="pd_mixed", action="store_false",
+                    help="the point detector also for Rayleigh events (default: mixed, Rayleigh "
+                         "pseudo-particles along their own law)")
     ap.add_argument("--pd-fraction", type=float, default=0.1,
                     help="point-detector photons as a fraction of the step's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -273,6 +277,18 @@ def main():
 
     def step():
         mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"], prim, scat, stream)
+
+    # launch shape from the autotuner (untimed; every candidate is checked
+    # bitwise against the first, the choice cached in the temp directory)
+    tuning = None
+    if not args.no_autotune:
+        import tempfile
+        log("autotune")
+        tuning = mcx.mc_autotune(g.ctx, w["angle"], min(n, 100_000_000), w["seed"] + 7,
+                                 os.path.join(tempfile.gettempdir(), "mcx_tune.jsonl"))
+        log(f"autotune: block {tuning['block']}, blocks/CU {tuning['blocks_per_cu']}, event batch "
+            f"{tuning['event_batch']}, table layout {tuning['table_layout']}, "
+            f"{tuning['candidates']} candidates, {tuning['rejected']} rejected")
 
     # exact algorithmic work of one step (untimed counting pass)
     log("counting pass")
@@ -337,7 +353,8 @@ def main():
     pd = None
     if args.pd_split > 0:
         n_pd = max(1, int(n * args.pd_fraction))
-        g.set_estimator(mcx.MC_SCORE_POINT, args.pd_split, args.pd_rr)
+        g.set_estimator(mcx.MC_SCORE_POINT_MIXED if args.pd_mixed else mcx.MC_SCORE_POINT,
+                        args.pd_split, args.pd_rr)
         mcx.mc_project_async(g.ctx, w["angle"], n_pd, w["seed"], prim, scat, stream)
         torch.cuda.synchronize()
         imgs, times = [], []
@@ -353,7 +370,8 @@ def main():
         t_pd = float(np.mean(times))
         r_pd = metrics.pair_rel_rms(*imgs)
         n2_pd = n_pd * (r_pd / 0.02) ** 2
-        pd = {"split": args.pd_split, "roulette_kev": args.pd_rr, "photons": n_pd,
+        pd = {"estimator": "mixed" if args.pd_mixed else "point", "split": args.pd_split,
+              "roulette_kev": args.pd_rr, "photons": n_pd,
               "ms_per_projection": t_pd * 1e3, "histories_per_s": n_pd / t_pd,
               "scatter_rel_rms": r_pd, "photons_for_2pct": n2_pd,
               "seconds_for_2pct": n2_pd * t_pd / n_pd,
@@ -441,6 +459,9 @@ def main():
             "photons_per_step": n,
             "step_mm": geo["step_mm"],
             "tallies": "int64 fixed point",
+            "launch": {k: tuning[k] for k in ("block", "blocks_per_cu", "event_batch",
+                                               "table_layout", "from_cache")} if tuning else
+                      "default",
         },
         "roofline": dict(roofline(st, gather_bytes, launch_s, args.workload, "transport_kernel"),
                          layout={0: "auto", 1: "palette-lane", 2: "palette-shared",

@@ -178,6 +178,13 @@ mc_status mc_set_detector_response(mc_ctx *ctx, const float *eta, int n);
  * MC_E_STATE).  Invalid mode, split or threshold: MC_E_INVALID_ARG. */
 #define MC_SCORE_ANALOG 0
 #define MC_SCORE_POINT 1
+/* MC_SCORE_POINT_MIXED: as MC_SCORE_POINT at Compton events; a Rayleigh
+ * event's pseudo-particles draw their directions from the Rayleigh law (their
+ * own Philox stream, counter (photon id, n, (i + 1) * 2^12 + block)) and score
+ * eta(E) / split * exp(-tau) where that line crosses the panel.  Same
+ * expectation; the form factor's forward peak gives eq. (5)'s random-point
+ * scores a heavy tail that this avoids. */
+#define MC_SCORE_POINT_MIXED 2
 mc_status mc_set_estimator(mc_ctx *ctx, int mode, int split, double rr_kev);
 
 /* Eq. (7), the primary image without Monte Carlo: d_out[nv*nu] (device fp32)
@@ -199,6 +206,42 @@ mc_status mc_primary_expected_async(mc_ctx *ctx, float angle_rad, int sub, float
  * and i+1 (map n_sim is map 0).  Stream-ordered. */
 mc_status mc_interp_angles_async(mc_ctx *ctx, const float *d_sim, int n_sim, uint64_t n_pix,
                                  float *d_full, void *stream);
+
+/* ---- the iterative scatter correction's reconstruction side (section II-E,
+ * its flowchart and eq. (8)).  Stream-ordered kernels on device buffers. */
+
+/* a[i] = -ln(I[i] / I0[i mod n0]) (fp32; I below 1e-30 taken as 1e-30): line
+ * integrals of n intensities, I0 the flat field of one projection (n0 pixels). */
+mc_status mc_line_integrals_async(mc_ctx *ctx, const float *d_I, uint64_t n, const float *d_I0,
+                                  uint64_t n0, float *d_a, void *stream);
+
+/* Eq. (8): c = a - ln(Ip / (Ip + Is)), elementwise over n values. */
+mc_status mc_scatter_correct_async(mc_ctx *ctx, const float *d_a, const float *d_ip,
+                                   const float *d_is, uint64_t n, float *d_c, void *stream);
+
+/* The FBP of the correction loop: Feldkamp-Davis-Kress cone-beam filtered
+ * backprojection for the context's orbit and panel (mc_set_geometry), full
+ * circle of n_ang equally spaced angles 2 pi i / n_ang.  d_proj[n_ang][nv][nu]
+ * line integrals -> d_vol[nz][ny][nx] attenuation (per mm), cubic voxels of
+ * voxel_mm centred on the axis; d_tmp holds the filtered projections (same
+ * size as d_proj).  Virtual panel through the axis, cosine pre-weight, the
+ * discrete Ram-Lak filter, distance-weighted bilinear backprojection.
+ * MC_E_INVALID_ARG for nu > 8192, n_ang > 4096, or a volume whose corners
+ * come within 1 % of the source orbit. */
+mc_status mc_fdk_async(mc_ctx *ctx, const float *d_proj, int n_ang, float *d_tmp, float *d_vol,
+                       int nx, int ny, int nz, float voxel_mm, void *stream);
+
+/* Histogram for Otsu's threshold: d_hist[bins] (uint32, cleared first) counts
+ * of x in [lo, hi), bin floor((x - lo) / (hi - lo) * bins). */
+mc_status mc_histogram_async(mc_ctx *ctx, const float *d_x, uint64_t n, float lo, float hi,
+                             int bins, uint32_t *d_hist, void *stream);
+
+/* Volume to density: voxels with mu >= threshold (per mm) get `material` and
+ * density mu / (0.1 mu_rho) (mu_rho in cm^2/g) rounded to multiples of step
+ * (g/cm^3); the others material 0 at its nominal density. */
+mc_status mc_to_density_async(mc_ctx *ctx, const float *d_mu, uint64_t n, float threshold,
+                              float mu_rho, int material, float step, uint8_t *d_ids,
+                              float *d_rho, void *stream);
 
 /* One projection, blocking: simulates photons 0 .. n_photons-1 (emitted into
  * the cone circumscribing the panel) with Philox key `seed`, and writes the

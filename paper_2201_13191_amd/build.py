@@ -26,6 +26,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math"
 HIP_FLAGS += [f"-D{d}" for d in os.environ.get("MCX_DEFINES", "").split()]
 
 SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
+           ("recon.hip", "hip"),
            ("probes.hip", "hip"),
            ("runtime.hip", "hip"),
            ("tables.cpp", "cxx"), ("cells.cpp", "cxx"), ("autotune.cpp", "hiphost")]

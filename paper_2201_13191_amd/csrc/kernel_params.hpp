@@ -116,6 +116,7 @@ struct KParams {
     // Russian-roulette threshold (keV, 0: off), and the series of the angular
     // laws' normalisations (Klein-Nishina kKnTerms, coherent kCohTerms)
     int pd_split;
+    int pd_mode;               // 1 point detector throughout, 2 mixed (Rayleigh along its law)
     double pd_rr;
     const double *kn_series;
     const double *coh_series;

@@ -42,6 +42,18 @@ hipError_t launch_primary(const KParams &p, int sub, const double *bin_w, const 
                           int n_bins, float *out, hipStream_t stream);
 hipError_t launch_interp_angles(const float *sim, int n_sim, uint64_t n_pix, float *full,
                                 hipStream_t stream);
+hipError_t launch_line_integrals(const float *I, uint64_t n, const float *I0, uint64_t n0,
+                                 float *a, hipStream_t s);
+hipError_t launch_scatter_correct(const float *a, const float *ip, const float *is, uint64_t n,
+                                  float *c, hipStream_t s);
+hipError_t launch_fdk(const float *proj, double R, double D, double pu, double pv, int nu, int nv,
+                      int n_ang, float *q, int nx, int ny, int nz, double h, float *vol,
+                      hipStream_t s);
+hipError_t launch_histogram(const float *x, uint64_t n, double lo, double hi, int bins,
+                            unsigned int *hist, hipStream_t s);
+hipError_t launch_to_density(const float *mu, uint64_t n, double threshold, double mu_rho,
+                             int material, double air_rho, double step, uint8_t *ids, float *rho,
+                             hipStream_t s);
 hipError_t launch_savgol(const float *in, float *out, float *tmp, int nx, int ny, int window,
                          const float *coeffs, hipStream_t s);
 hipError_t launch_flip2d(const float *in, float *out, int nx, int ny, int fx, int fy, float alpha,
@@ -447,7 +459,10 @@ mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t se
     p.key0 = (uint32_t)seed;
     p.key1 = (uint32_t)(seed >> 32);
     p.counter = c->d_ctl + (c->launches++ % kRing);
-    if (c->estimator == MC_SCORE_POINT) p.pd_split = c->pd_split;
+    if (c->estimator != MC_SCORE_ANALOG) {
+        p.pd_split = c->pd_split;
+        p.pd_mode = c->estimator == MC_SCORE_POINT_MIXED ? 2 : 1;
+    }
     return MC_OK;
 }
 
@@ -1313,9 +1328,85 @@ mc_status mc_interp_angles_async(mc_ctx *c, const float *d_sim, int n_sim, uint6
     return MC_OK;
 }
 
+mc_status mc_line_integrals_async(mc_ctx *c, const float *d_I, uint64_t n, const float *d_I0,
+                                  uint64_t n0, float *d_a, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_I || !d_I0 || !d_a || n0 < 1 || n < 1 || n % n0)
+        return fail(c, MC_E_INVALID_ARG, "need buffers and n a multiple of n0 >= 1");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    hipError_t e = launch_line_integrals(d_I, n, d_I0, n0, d_a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "line integrals");
+    return MC_OK;
+}
+
+mc_status mc_scatter_correct_async(mc_ctx *c, const float *d_a, const float *d_ip,
+                                   const float *d_is, uint64_t n, float *d_c, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_a || !d_ip || !d_is || !d_c || n < 1) return fail(c, MC_E_INVALID_ARG, "bad buffers");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    hipError_t e = launch_scatter_correct(d_a, d_ip, d_is, n, d_c, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "scatter correction");
+    return MC_OK;
+}
+
+mc_status mc_fdk_async(mc_ctx *c, const float *d_proj, int n_ang, float *d_tmp, float *d_vol,
+                       int nx, int ny, int nz, float voxel_mm, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!c->have_geom) return fail(c, MC_E_STATE, "geometry not set");
+    if (!d_proj || !d_tmp || !d_vol || n_ang < 1 || nx < 1 || ny < 1 || nz < 1 ||
+        !(voxel_mm > 0.0f) || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return fail(c, MC_E_INVALID_ARG, "bad reconstruction arguments");
+    // LDS: one panel row (fp64) per filter block, cos/sin of every angle per
+    // backprojection block, 64 KiB each at most
+    if (c->g.nu > 8192 || n_ang > 4096)
+        return fail(c, MC_E_INVALID_ARG, "FDK supports nu <= 8192 and n_ang <= 4096");
+    // every voxel strictly inside the source orbit (the distance weight's
+    // L = R - x.s stays positive)
+    const double hx = 0.5 * nx * (double)voxel_mm, hy = 0.5 * ny * (double)voxel_mm;
+    if (!(sqrt(hx * hx + hy * hy) < 0.99 * (double)c->g.sod_mm))
+        return fail(c, MC_E_INVALID_ARG, "volume reaches the source orbit");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    const mc_geometry &g = c->g;
+    hipError_t e = launch_fdk(d_proj, g.sod_mm, g.sdd_mm, g.pu_mm, g.pv_mm, g.nu, g.nv, n_ang,
+                              d_tmp, nx, ny, nz, voxel_mm, d_vol, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fdk");
+    return MC_OK;
+}
+
+mc_status mc_histogram_async(mc_ctx *c, const float *d_x, uint64_t n, float lo, float hi,
+                             int bins, uint32_t *d_hist, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_x || !d_hist || bins < 1 || bins > 65536 || !(hi > lo))
+        return fail(c, MC_E_INVALID_ARG, "bad histogram arguments");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    hipError_t e = launch_histogram(d_x, n, lo, hi, bins, d_hist, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "histogram");
+    return MC_OK;
+}
+
+mc_status mc_to_density_async(mc_ctx *c, const float *d_mu, uint64_t n, float threshold,
+                              float mu_rho, int material, float step, uint8_t *d_ids,
+                              float *d_rho, void *stream) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!d_mu || !d_ids || !d_rho || !(mu_rho > 0.0f) || !(step > 0.0f) || material < 1 ||
+        material >= (int)c->mats.size())
+        return fail(c, MC_E_INVALID_ARG, "bad density arguments");
+    mc_status rc = use_device(c);
+    if (rc) return rc;
+    hipError_t e = launch_to_density(d_mu, n, threshold, mu_rho, material,
+                                     (double)c->mats[0].rho_default, step, d_ids, d_rho,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "to density");
+    return MC_OK;
+}
+
 mc_status mc_set_estimator(mc_ctx *c, int mode, int split, double rr_kev) {
     if (!c) return MC_E_INVALID_ARG;
-    if (mode != MC_SCORE_ANALOG && mode != MC_SCORE_POINT)
+    if (mode != MC_SCORE_ANALOG && mode != MC_SCORE_POINT && mode != MC_SCORE_POINT_MIXED)
         return fail(c, MC_E_INVALID_ARG, "unknown estimator %d", mode);
     if (split < 1 || split > 1024) return fail(c, MC_E_INVALID_ARG, "split must be 1..1024");
     if (!(rr_kev >= 0.0) || !std::isfinite(rr_kev))

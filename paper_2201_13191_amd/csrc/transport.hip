@@ -48,11 +48,16 @@ __device__ __forceinline__ float unit_float(uint32_t x) {
     return (float)(2u * (x >> 9) + 1u) * 5.9604644775390625e-8f;
 }
 
-struct PhotonStream {
+// A photon's stream: counter (photon id, block, 0).  PSEUDO: the stream of
+// pseudo-particle i of the photon's n-th scattering, counter
+// (photon id, n, (i + 1) * 2^12 + block).
+template <bool PSEUDO>
+struct StreamT {
     uint32_t id_lo, id_hi, key0, key1;
     uint32_t next;     // index of the next draw
     uint32_t cached;   // block index held in w0 .. w3
     uint32_t w0, w1, w2, w3;
+    uint32_t n, tag;   // PSEUDO only
 
     __device__ void reset(uint64_t photon, uint32_t k0, uint32_t k1) {
         id_lo = (uint32_t)photon;
@@ -62,10 +67,20 @@ struct PhotonStream {
         next = 0;
         cached = 0xFFFFFFFFu;
     }
+    __device__ void reset_pseudo(uint64_t photon, uint32_t k0, uint32_t k1, uint32_t scat,
+                                 uint32_t i) {
+        reset(photon, k0, k1);
+        n = scat;
+        tag = (i + 1u) << 12;
+    }
+    __device__ __forceinline__ uint4 block(uint32_t b) const {
+        return PSEUDO ? philox4x32_10(make_uint4(id_lo, id_hi, n, tag | b), key0, key1)
+                      : philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+    }
     __device__ uint32_t raw() {
         const uint32_t b = next >> 2;
         if (b != cached) {
-            const uint4 blk = philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+            const uint4 blk = block(b);
             w0 = blk.x;
             w1 = blk.y;
             w2 = blk.z;
@@ -93,7 +108,7 @@ struct PhotonStream {
         uint32_t x0 = w0, x1 = w1, x2 = w2, x3 = w3;   // the block before the new one
         if (fresh || straddle) {
             const uint32_t b = fresh ? b0 : b1;
-            const uint4 blk = philox4x32_10(make_uint4(id_lo, id_hi, b, 0u), key0, key1);
+            const uint4 blk = block(b);
             w0 = blk.x;
             w1 = blk.y;
             w2 = blk.z;
@@ -121,6 +136,8 @@ struct PhotonStream {
         next += (uint32_t)N;
     }
 };
+using PhotonStream = StreamT<false>;
+using PseudoStream = StreamT<true>;
 
 // ------------------------------------------------------------------ tables
 __device__ __forceinline__ float grid_lerp(const float *t, int J, float e) {
@@ -180,7 +197,8 @@ __device__ void sample_compton(PhotonStream &s, float e, float &ct, float &e_out
 // Rayleigh polar angle: v = sin^2(theta/2)/lambda^2 inverted from the
 // (1 + b v)^-4 form-factor weight, accepted with (1 + cos^2)/2 evaluated on
 // the fp32 cosine.  One trial (two draws); the cosine is set either way.
-__device__ __forceinline__ bool rayleigh_trial(PhotonStream &s, float e, double b, float &cf) {
+template <class S>
+__device__ __forceinline__ bool rayleigh_trial(S &s, float e, double b, float &cf) {
     const double t = (double)e / 12.398419843320026;
     const double V = t * t;
     const double W = 1.0 + b * V;
@@ -196,7 +214,8 @@ __device__ __forceinline__ bool rayleigh_trial(PhotonStream &s, float e, double 
     return r2 <= 0.5 * (1.0 + cd * cd);
 }
 
-__device__ float sample_rayleigh(PhotonStream &s, float e, double b) {
+template <class S>
+__device__ float sample_rayleigh(S &s, float e, double b) {
     float cf;
     while (!rayleigh_trial(s, e, b, cf)) {
     }
@@ -674,6 +693,47 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     };
     auto pd_start = [&]() __attribute__((always_inline)) -> bool {
         const ProjFrame &F = p.F;
+        if (p.pd_mode == 2 && pd_rayl) {
+            // mixed estimator: a Rayleigh pseudo-particle draws its direction
+            // from the Rayleigh law (its own stream) and scores eta(E) / split
+            // exp(-tau) where that line crosses the panel
+            PseudoStream ps;
+            ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)n_int, (uint32_t)pd_i);
+            const float ct = sample_rayleigh(ps, e, p.rayl_b[mat]);
+            double sphi, cphi;
+            sincos(6.283185307179586 * (double)ps.u(), &sphi, &cphi);
+            float om[3] = {d[0], d[1], d[2]};
+            rotate_direction(om[0], om[1], om[2], ct, sqrtf(fmaxf(0.0f, 1.0f - ct * ct)),
+                             (float)cphi, (float)sphi);
+            int iu, iv;
+            if (!panel_hit(p, F, o, om, iu, iv)) return false;
+            double x0 = (double)grid_lerp(p.eta, p.J, e) / (double)p.pd_split;
+            const double u_rr = (double)ps.u();
+            if (p.pd_rr > 0.0 && x0 < p.pd_rr) {
+                if (u_rr < x0 / p.pd_rr) {
+                    x0 = p.pd_rr;
+                } else {
+                    if (STATS) ++st[kStPdKilled];
+                    return false;
+                }
+            }
+            pd_x0 = x0;
+            pd_bin = (uint32_t)((iv / p.bv) * p.snu + iu / p.bu);
+            float tout;
+            if (!box_entry(p.G, o, om, tin, tout)) {
+                pd_score(0.0);
+                return false;
+            }
+            if (tab_e != e) {
+                refresh_mu(e, p.G);
+                tab_e = e;
+            }
+            start_march(p.G, om, tout);
+            ts = __builtin_inf();
+            pd_flight = true;
+            if (STATS) ++st[kStFlights];
+            return true;
+        }
         const uint4 w = philox4x32_10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32),
                                                  (uint32_t)n_int, (uint32_t)pd_i + 1u),
                                       p.key0, p.key1);

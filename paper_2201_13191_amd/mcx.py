@@ -35,7 +35,9 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
            "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator",
            "mc_set_batch_launch", "mc_get_batch_info", "mc_autotune_batch",
-           "mc_primary_expected_async", "mc_interp_angles_async"]
+           "mc_primary_expected_async", "mc_interp_angles_async", "mc_line_integrals_async",
+           "mc_scatter_correct_async", "mc_fdk_async", "mc_histogram_async",
+           "mc_to_density_async"]
 MC_BATCH_GRAPH = 1
 MC_LAYOUT_AUTO, MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED, MC_LAYOUT_GENERIC = 0, 1, 2, 3
 
@@ -131,6 +133,11 @@ def load():
         "mc_set_estimator": ([P, I, I, C.c_double], I),
         "mc_set_batch_launch": ([P, I, I, I], I),
         "mc_primary_expected_async": ([P, F, I, P, P], I),
+        "mc_line_integrals_async": ([P, P, U64, P, U64, P, P], I),
+        "mc_scatter_correct_async": ([P, P, P, P, U64, P, P], I),
+        "mc_fdk_async": ([P, P, I, P, P, I, I, I, F, P], I),
+        "mc_histogram_async": ([P, P, U64, F, F, I, P, P], I),
+        "mc_to_density_async": ([P, P, U64, F, F, I, F, P, P, P], I),
         "mc_interp_angles_async": ([P, P, I, U64, P, P], I),
         "mc_get_batch_info": ([P, C.POINTER(I), C.POINTER(U64), C.POINTER(I)], I),
         "mc_autotune_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_char_p, C.POINTER(mc_tuning)], I),
@@ -237,7 +244,7 @@ def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=N
                                         _stream(stream)))
 
 
-MC_SCORE_ANALOG, MC_SCORE_POINT = 0, 1
+MC_SCORE_ANALOG, MC_SCORE_POINT, MC_SCORE_POINT_MIXED = 0, 1, 2
 
 
 def mc_set_estimator(ctx, mode, split=1, rr_kev=0.0):
@@ -391,6 +398,37 @@ def mc_interp_angles_async(ctx, d_sim, n_sim, n_pix, d_full, stream=None):
     """Every-other-angle scatter maps [n_sim, n_pix] -> [2 n_sim, n_pix] (device fp32)."""
     _check(ctx, load().mc_interp_angles_async(ctx, _dev(d_sim), n_sim, n_pix, _dev(d_full),
                                               _stream(stream)))
+
+
+def mc_line_integrals_async(ctx, d_I, d_I0, d_a, stream=None):
+    """a = -ln(I / I0) (device fp32; I0 one projection, repeated)."""
+    _check(ctx, load().mc_line_integrals_async(ctx, _dev(d_I), d_I.numel(), _dev(d_I0),
+                                               d_I0.numel(), _dev(d_a), _stream(stream)))
+
+
+def mc_scatter_correct_async(ctx, d_a, d_ip, d_is, d_c, stream=None):
+    """Eq. (8): c = a - ln(Ip / (Ip + Is)) (device fp32, same sizes)."""
+    _check(ctx, load().mc_scatter_correct_async(ctx, _dev(d_a), _dev(d_ip), _dev(d_is),
+                                                d_a.numel(), _dev(d_c), _stream(stream)))
+
+
+def mc_fdk_async(ctx, d_proj, d_tmp, d_vol, voxel_mm, stream=None):
+    """FDK of d_proj [n_ang, nv, nu] into d_vol [nz, ny, nx] (device fp32)."""
+    n_ang = d_proj.shape[0]
+    nz, ny, nx = d_vol.shape
+    _check(ctx, load().mc_fdk_async(ctx, _dev(d_proj), n_ang, _dev(d_tmp), _dev(d_vol), nx, ny,
+                                    nz, voxel_mm, _stream(stream)))
+
+
+def mc_histogram_async(ctx, d_x, lo, hi, bins, d_hist, stream=None):
+    _check(ctx, load().mc_histogram_async(ctx, _dev(d_x), d_x.numel(), lo, hi, bins, _dev(d_hist),
+                                          _stream(stream)))
+
+
+def mc_to_density_async(ctx, d_mu, threshold, mu_rho, material, step, d_ids, d_rho, stream=None):
+    _check(ctx, load().mc_to_density_async(ctx, _dev(d_mu), d_mu.numel(), threshold, mu_rho,
+                                           material, step, _dev(d_ids), _dev(d_rho),
+                                           _stream(stream)))
 
 
 def mc_set_batch_launch(ctx, block=0, blocks_per_cu=0, event_batch=0):

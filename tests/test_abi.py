@@ -214,7 +214,7 @@ def test_make_kramers_arguments(lib):
 def test_estimator_arguments(host_ctx):
     mcx.mc_set_estimator(host_ctx, mcx.MC_SCORE_POINT, 8, 0.5)
     mcx.mc_set_estimator(host_ctx, mcx.MC_SCORE_ANALOG)
-    for bad in [(2, 1, 0.0), (1, 0, 0.0), (1, 1025, 0.0), (1, 4, -1.0), (1, 4, float("inf")),
+    for bad in [(3, 1, 0.0), (1, 0, 0.0), (1, 1025, 0.0), (1, 4, -1.0), (1, 4, float("inf")),
                 (1, 4, float("nan"))]:
         with pytest.raises(mcx.MCXError):
             mcx.mc_set_estimator(host_ctx, *bad)

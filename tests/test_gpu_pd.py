@@ -30,16 +30,20 @@ def gpu():
     return torch
 
 
-def _run(name, ids, rho, h, geo, spec, n, seed, split, rr, angle=0.3, layout=None):
+MODES = [(oracle.SCORE_POINT, mcx.MC_SCORE_POINT), (oracle.SCORE_POINT_MIXED, mcx.MC_SCORE_POINT_MIXED)]
+
+
+def _run(name, ids, rho, h, geo, spec, n, seed, split, rr, angle=0.3, layout=None,
+         modes=MODES[0]):
     o, g = pair(ids, rho, h, geo, spec)
     if layout is not None:
         g.set_layout(layout)
         g.load_phantom(ids, rho, h)
     say(name, "analog GPU")
     pa, sa = g.project(angle, n, seed)
-    for side, mode in ((o, oracle.SCORE_POINT), (g, mcx.MC_SCORE_POINT)):
+    for side, mode in zip((o, g), modes):
         side.set_estimator(mode, split, rr)
-    say(name, f"point detector split {split} rr {rr}, {n} photons")
+    say(name, f"estimator {modes[1]} split {split} rr {rr}, {n} photons")
     g.stats(True)
     pg, sg = g.project(angle, n, seed)
     st_g = g.stats()
@@ -61,20 +65,22 @@ def _run(name, ids, rho, h, geo, spec, n, seed, split, rr, angle=0.3, layout=Non
     return sg, so
 
 
-def test_pd_cylinder(gpu):
+@pytest.mark.parametrize("modes", MODES, ids=["point", "mixed"])
+def test_pd_cylinder(gpu, modes):
     w = inputs.workload("cylinder64")
     _run("cylinder64", w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"],
-         100_000, 0, 4, 0.0)
+         100_000, 0, 4, 0.0, modes=modes)
 
 
+@pytest.mark.parametrize("modes", MODES, ids=["point", "mixed"])
 @pytest.mark.parametrize("layout", [mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED,
                                     mcx.MC_LAYOUT_GENERIC])
-def test_pd_layouts_with_roulette(gpu, layout):
+def test_pd_layouts_with_roulette(gpu, layout, modes):
     ids, rho = inputs.ellipsoid_phantom(48, 1.0, seed=31)
     geo = dict(sod_mm=300.0, sdd_mm=600.0, nu=64, nv=48, pu_mm=2.0, pv_mm=2.0, snu=16, snv=12,
                step_mm=0.7, flags=0)
     _run(f"ellipsoids48 layout {layout}", ids, rho, 1.0, geo, inputs.kramers_spectrum(120, 2.0),
-         60_000, 5, 6, 0.02, layout=layout)
+         60_000, 5, 6, 0.02, layout=layout, modes=modes)
 
 
 def test_pd_long_steps_and_iron(gpu):
@@ -83,8 +89,9 @@ def test_pd_long_steps_and_iron(gpu):
     ids, rho = inputs.ellipsoid_phantom(40, 1.0, seed=8, materials=(1, 2, 3), iron_insert=True)
     geo = dict(sod_mm=200.0, sdd_mm=400.0, nu=40, nv=40, pu_mm=4.0, pv_mm=4.0, snu=10, snv=10,
                step_mm=1.7, flags=0)
-    _run("iron, long steps", ids, rho, 1.0, geo, inputs.kramers_spectrum(60, 0.5), 50_000, 9, 3,
-         0.0, angle=1.1)
+    for modes in MODES:
+        _run("iron, long steps", ids, rho, 1.0, geo, inputs.kramers_spectrum(60, 0.5), 50_000, 9,
+             3, 0.0, angle=1.1, modes=modes)
 
 
 def test_pd_full_size_subrange(gpu):
@@ -93,7 +100,7 @@ def test_pd_full_size_subrange(gpu):
     torch = gpu
     w = inputs.workload("ellipsoids256_poly")
     o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"])
-    for side, mode in ((o, oracle.SCORE_POINT), (g, mcx.MC_SCORE_POINT)):
+    for side, mode in zip((o, g), MODES[1]):
         side.set_estimator(mode, 8, 0.0)
     geo = w["geometry"]
     a, m = 50_000_123, 20_000
@@ -117,7 +124,7 @@ def test_pd_launch_shapes_and_ranges(gpu):
     g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
     g.set_geometry(**w["geometry"])
     g.set_spectrum(*inputs.kramers_spectrum(100, 1.0))
-    g.set_estimator(mcx.MC_SCORE_POINT, 5, 0.01)
+    g.set_estimator(mcx.MC_SCORE_POINT_MIXED, 5, 0.01)
     say("point detector launch shapes")
     ref = g.project(0.7, 150_000, 11)
     for block, bpc, spr in [(64, 1, 1), (128, 2, 7), (192, 0, 64), (256, 0, 33)]:
