@@ -21,6 +21,7 @@ END_PRIMARY, END_SCATTER, END_MISSED, END_PHOTO, END_CUTOFF, END_CAP = range(6)
 FIRST_NONE, FIRST_PHOTO, FIRST_RAYLEIGH, FIRST_COMPTON = range(4)
 READING_GRID, READING_PLAIN = 0, 1
 SCORE_ANALOG, SCORE_POINT, SCORE_POINT_MIXED = 0, 1, 2
+PHYS_INCOH_SF, PHYS_DOPPLER = 1, 2      # binding effects (set_physics)
 
 
 class Material(C.Structure):
@@ -40,7 +41,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "histories", "steps", "flights", "photo", "rayleigh", "compton",
         "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits",
-        "pd_scores", "pd_killed", "pd_steps")]
+        "pd_scores", "pd_killed", "pd_steps", "null_collisions")]
 
 
 _lib = None
@@ -74,6 +75,7 @@ def lib():
                                       P, P, P]
         L.mco_set_reading.argtypes = [P, C.c_int]
         L.mco_set_estimator.argtypes = [P, C.c_int, C.c_int, C.c_double]
+        L.mco_set_physics.argtypes = [P, C.c_uint32]
         L.mco_primary_expected.argtypes = [P, C.c_float, C.c_int, P]
         L.mco_interp_angles.argtypes = [P, C.c_int, C.c_int64, P]
         L.mco_pd_pdf.argtypes = [P, C.c_int, C.c_int, C.c_float, C.c_double,
@@ -213,6 +215,11 @@ class Oracle:
     def set_reading(self, reading):
         self._check(self._L.mco_set_reading(self._h, reading))
 
+    def set_physics(self, flags):
+        """Binding effects: PHYS_INCOH_SF (S(x,Z) of eq. (1) as null
+        collisions) | PHYS_DOPPLER (broadened Compton energies)."""
+        self._check(self._L.mco_set_physics(self._h, int(flags)))
+
     def set_estimator(self, mode, split=1, rr_kev=0.0):
         """SCORE_ANALOG, or SCORE_POINT: the point-detector estimator of eq.
         (3)-(5) with `split` pseudo-particles per scattering and Russian
@@ -265,11 +272,12 @@ class Oracle:
         J = C.c_int()
         self._check(self._L.mco_get_tables(self._h, C.byref(J), None, None, None, None))
         J = J.value
-        pe, coh, inc = (np.zeros((n_mat, J), np.float32) for _ in range(3))
+        # the oracle writes every material it holds (at most 16): room for all
+        pe, coh, inc = (np.zeros((16, J), np.float32) for _ in range(3))
         eta = np.zeros(J, np.float32)
         self._check(self._L.mco_get_tables(self._h, C.byref(C.c_int()), _ptr(pe), _ptr(coh),
                                            _ptr(inc), _ptr(eta)))
-        return pe, coh, inc, eta
+        return pe[:n_mat].copy(), coh[:n_mat].copy(), inc[:n_mat].copy(), eta
 
     def stats(self):
         s = Stats()

@@ -40,6 +40,8 @@
 #define N_AVO 6.02214076e23L
 /* h*c in keV*Angstrom: lambda[A] = HC / E[keV] */
 #define HC_KEV_A 12.398419843320026
+/* inverse fine-structure constant (CODATA 2018) */
+#define ALPHA_INV 137.035999084
 /* Bohr radius, Angstrom */
 #define BOHR_A 0.529177210903
 /* parametric photoelectric constant per electron, cm^2 keV^3 (times Z^3) */
@@ -57,6 +59,8 @@ struct mco_ctx {
     int n_mat;
     mco_material mat[MAX_MAT];
     double rayl_b[MAX_MAT];     /* (2 pi r_Z)^2 [A^2], screening of F(x,Z) */
+    double pz_scale[MAX_MAT];   /* Compton-profile momentum scale / (m c)   */
+    uint32_t phys;              /* MCO_PHYS_* binding effects              */
     int nx, ny, nz;
     float h;
     uint8_t *ids;
@@ -251,6 +255,9 @@ static void set_mats(mco_ctx *c, const mco_material *m, int n) {
         double rz = 0.885 * BOHR_A / cbrt((double)m[i].z_eff);
         double t = TWO_PI_D * rz;
         c->rayl_b[i] = t * t;
+        /* the orbital of radius r_Z has momentum scale hbar / r_Z = (a0 / r_Z)
+         * atomic units; one atomic unit of momentum is m c / ALPHA_INV */
+        c->pz_scale[i] = (cbrt((double)m[i].z_eff) / 0.885) / ALPHA_INV;
     }
     c->tables_dirty = 1;
 }
@@ -522,8 +529,7 @@ int mco_detector_pixel(mco_ctx *c, float beta, const float p[3], const float d[3
  * x = E/E' in [1, 1 + 2 alpha] from two branches, accepted against the
  * Klein-Nishina shape; three draws per trial.  fp64, correctly rounded
  * operations only. */
-static void sample_compton(rng_t *r, float e, float *cos_out, float *e_out) {
-    double alpha = (double)e / MEC2_KEV;
+static double kahn_x(rng_t *r, double alpha) {
     double x;
     for (;;) {
         double r1 = (double)rng_u(r);
@@ -538,8 +544,7 @@ static void sample_compton(rng_t *r, float e, float *cos_out, float *e_out) {
             if (r3 <= 0.5 * (c * c + 1.0 / x)) break;
         }
     }
-    *e_out = (float)((double)e / x);
-    *cos_out = (float)(1.0 - (x - 1.0) / alpha);
+    return x;
 }
 
 /* Rayleigh polar angle for eq. (2): v = x^2 drawn from F^2 ~ (1 + b v)^-4 on
@@ -559,6 +564,95 @@ static float sample_rayleigh(rng_t *r, float e, double b) {
         double cd = (double)cf;
         if (r2 <= 0.5 * (1.0 + cd * cd)) return cf;
     }
+}
+
+/* ------------------------------------------------------------ binding effects
+ * Eq. (1) carries the incoherent scattering function S(x,Z), and the Compton
+ * line is broadened by the motion of the bound electrons (section II-A); the
+ * paper takes both from tabulated atomic data, which this build does not
+ * have.  Parametric stand-ins from one orbital model: every electron of a
+ * material sits in a hydrogen-like 1s orbital whose radius is the screening
+ * radius r_Z = 0.885 a0 Z^(-1/3) of the Rayleigh form factor above.  Then
+ *   F(x,Z)/Z = (1 + b x^2)^-2               (the form factor already in use),
+ *   S(x,Z)/Z = 1 - (F/Z)^2 = 1 - (1 + b x^2)^-4     (independent electrons),
+ *   J(p_z)   = 8 / (3 pi p0) (1 + (p_z / p0)^2)^-3,   p0 = hbar / r_Z,
+ * the last being the 1s Compton profile (x = sin(theta/2) / lambda of the
+ * incoming photon, b = (2 pi r_Z)^2).
+ *
+ * S by rejection, as a null collision: the tables keep the Klein-Nishina cross
+ * section; a Compton collision draws Kahn's angle and is accepted with
+ * probability S/Z; a rejected one leaves the photon as it was (direction,
+ * energy, primary or scattered), so the effective cross section (the KN
+ * integral of S/Z) and the angular law (KN times S/Z) are both exact.
+ *
+ * Doppler broadening: s = |p_z| / p0 is drawn from (1 + s^2)^-3 by rejection
+ * from the envelope (1 + s)^-2 (inverted exactly: s = a / (1 - a), a uniform),
+ * accepted with (1 + s)^2 / (M (1 + s^2)^3), M = 1.3064 above the ratio's
+ * maximum (at s = (sqrt(17) - 3) / 4); the sign of p_z comes with the same
+ * draw.  The scattered energy then solves the impulse-approximation relation
+ * P = p_z / (m c) = (r / tau - 1) / sqrt(1 + r^2 - 2 r mu) for r = E'/E, tau =
+ * E_KN / E the Compton ratio at the sampled cosine mu: with t = P^2,
+ *   r = tau ((1 - t tau mu) +- sqrt((1 - t tau mu)^2 - (1 - t tau^2)(1 - t))) / (1 - t tau^2),
+ * the sign that of P.  A draw without a root in (0, 1) is drawn again; the
+ * draws with p_z < 0 always have one when tau < 1, so the loop ends. */
+#define DOPPLER_ENVELOPE 1.3064
+
+/* S(x,Z)/Z at b [A^2], V = 1/lambda^2 [A^-2] and om = 1 - cos(theta) */
+static double incoh_sf(double b, double V, double om) {
+    const double w = 1.0 + b * (0.5 * V * om);
+    const double w2 = w * w;
+    return 1.0 - 1.0 / (w2 * w2);
+}
+
+/* one trial of the broadened ratio E'/E (pz = p0 / (m c)); 0 if rejected */
+static int doppler_trial(rng_t *r, double pz, double tau, double mu, double *ratio) {
+    const double v = 2.0 * (double)rng_u(r) - 1.0;
+    const double u2 = (double)rng_u(r);
+    const double a = fabs(v);
+    const double s = a / (1.0 - a);
+    const double s2 = 1.0 + s * s;
+    if (!(u2 * DOPPLER_ENVELOPE <= ((1.0 + s) * (1.0 + s)) / ((s2 * s2) * s2))) return 0;
+    const double P = (v < 0.0 ? -s : s) * pz;
+    const double t = P * P;
+    const double c1 = 1.0 - (t * tau) * mu;
+    const double c2 = 1.0 - (t * tau) * tau;
+    const double disc = c1 * c1 - c2 * (1.0 - t);
+    if (!(c2 > 0.0) || !(disc >= 0.0)) return 0;
+    const double root = sqrt(disc);
+    const double x = tau * ((P < 0.0 ? c1 - root : c1 + root) / c2);
+    if (!(x > 0.0 && x < 1.0)) return 0;
+    *ratio = x;
+    return 1;
+}
+
+static double sample_doppler(rng_t *r, double pz, double tau, double mu) {
+    /* no momentum transfer (a point-detector direction along the photon's
+     * own): the line is not shifted, and no r < 1 solves the relation */
+    if (!(tau < 1.0)) return 1.0;
+    double x;
+    while (!doppler_trial(r, pz, tau, mu, &x)) {
+    }
+    return x;
+}
+
+/* One Compton collision of the transport: Kahn's angle; with
+ * MCO_PHYS_INCOH_SF one more draw accepts it with S/Z (0 returned: a null
+ * collision); with MCO_PHYS_DOPPLER the broadened energy. */
+static int compton_collision(const mco_ctx *c, rng_t *r, int m, float e, float *ct, float *e2) {
+    const double alpha = (double)e / MEC2_KEV;
+    const double x = kahn_x(r, alpha);
+    if (c->phys & MCO_PHYS_INCOH_SF) {
+        const double t = (double)e / HC_KEV_A;
+        const double u = (double)rng_u(r);
+        if (!(u <= incoh_sf(c->rayl_b[m], t * t, (x - 1.0) / alpha))) return 0;
+    }
+    *ct = (float)(1.0 - (x - 1.0) / alpha);
+    if (c->phys & MCO_PHYS_DOPPLER)
+        *e2 = (float)((double)e * sample_doppler(r, c->pz_scale[m], 1.0 / x,
+                                                 1.0 - (x - 1.0) / alpha));
+    else
+        *e2 = (float)((double)e / x);
+    return 1;
 }
 
 /* new direction after scattering by polar cosine ct and azimuth (cp, sp) */
@@ -797,7 +891,14 @@ static double pd_pdf(const mco_ctx *c, int proc, int m, float e, double lam, flo
         const double ratio = 1.0 + alpha * (1.0 - lam);     /* E / E' = alpha / alpha' */
         const double r = 1.0 / ratio;
         *e_out = (float)((double)e / ratio);
-        return r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(e);
+        double pdf = r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(e);
+        if (c->phys & MCO_PHYS_INCOH_SF) {
+            /* a collision sends its photon into lam with KN S/Z: the law's
+             * deficit is the null collisions' share, which scores nothing */
+            const double t = (double)e / HC_KEV_A;
+            pdf *= incoh_sf(c->rayl_b[m], t * t, 1.0 - lam);
+        }
+        return pdf;
     }
     /* Rayleigh: (1 + lam^2) F^2 with F = Z / (1 + b x^2)^2, x^2 = (1 - lam)/2 / wavelength^2;
      * over lam in [-1, 1] the unnormalised density integrates to 2 Z^2 G(b V) */
@@ -858,10 +959,10 @@ static void pd_rayleigh_along_law(const mco_ctx *c, const proj_t *P, uint64_t se
     st->pd_scores++;
 }
 
-static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t pid, int n,
-                     const float o[3], const float d[3], float e, int m, int proc,
-                     int64_t *scat, mco_stats *st) {
-    if (n + 1 >= MAX_SCATTER) return;     /* the scattered photon is not transported */
+static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t pid,
+                     int n_int, int n, const float o[3], const float d[3], float e, int m,
+                     int proc, int64_t *scat, mco_stats *st) {
+    if (n_int + 1 >= MAX_SCATTER) return;     /* the scattered photon is not transported */
     const mco_geometry *g = &c->g;
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     const double area = (double)((float)g->nu * g->pu_mm) * (double)((float)g->nv * g->pv_mm);
@@ -895,6 +996,15 @@ static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t 
             dist;
         float e2;
         const double pdf = pd_pdf(c, proc, m, e, lam, &e2);
+        if (proc == MCO_PROC_COMPTON && (c->phys & MCO_PHYS_DOPPLER)) {
+            /* the broadened energy towards the point, from the pseudo-particle's
+             * own stream */
+            rng_t rd;
+            rng_init_pseudo(&rd, seed, pid, (uint32_t)n, (uint32_t)i);
+            const double alpha = (double)e / MEC2_KEV;
+            const double ratio = 1.0 + alpha * (1.0 - lam);
+            e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));
+        }
         if (e2 < E_CUT_KEV) continue;       /* such a photon would be killed */
         const double eta = (double)lerp_tab(c->t_eta, c->J, e2);
         double x0 = (((eta * pdf) * cg) * area) / ((TWO_PI_D * r2) * (double)c->split);
@@ -941,7 +1051,8 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
     birth(c, P, &r, &e, d);
     for (int a = 0; a < 3; ++a) p[a] = P->S[a];
     mat_mu(c, e, mm);
-    int n_int = 0;
+    int n_int = 0;     /* scatterings                                  */
+    int n_coll = 0;    /* scatterings and null collisions: PD counters */
     for (;;) {
         float tin, tout;
         if (!box_hit(P, p, d, &tin, &tout)) break;
@@ -977,21 +1088,28 @@ static void history(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t p
             h->e_end = e;
             return;
         }
-        float ct, e2;
+        float ct = 1.0f, e2 = e;
+        int real = 1;
         if (x < pe + coh) {
             ct = sample_rayleigh(&r, e, c->rayl_b[m]);
             e2 = e;
             st->rayleigh++;
             if (!n_int) h->first = MCO_FIRST_RAYLEIGH;
         } else {
-            sample_compton(&r, e, &ct, &e2);
-            st->compton++;
-            if (!n_int) h->first = MCO_FIRST_COMPTON;
+            real = compton_collision(c, &r, m, e, &ct, &e2);
+            if (real) {
+                st->compton++;
+                if (!n_int) h->first = MCO_FIRST_COMPTON;
+            } else {
+                st->null_collisions++;
+            }
         }
         double phi = TWO_PI_D * (double)rng_u(&r);
         if (c->estimator != MCO_SCORE_ANALOG && scat)
-            pd_event(c, P, seed, pid, n_int, p, d, e, m,
+            pd_event(c, P, seed, pid, n_int, n_coll, p, d, e, m,
                      x < pe + coh ? MCO_PROC_RAYLEIGH : MCO_PROC_COMPTON, scat, st);
+        n_coll++;
+        if (!real) continue;     /* null collision: the same flight goes on */
         rotate(d, ct, (float)cos(phi), (float)sin(phi));
         n_int++;
         if (e2 < E_CUT_KEV) {
@@ -1047,6 +1165,7 @@ static void stats_add(mco_stats *a, const mco_stats *b) {
     a->primary_hits += b->primary_hits; a->scatter_hits += b->scatter_hits;
     a->cutoff_kills += b->cutoff_kills; a->cap_hits += b->cap_hits;
     a->pd_scores += b->pd_scores; a->pd_killed += b->pd_killed; a->pd_steps += b->pd_steps;
+    a->null_collisions += b->null_collisions;
 }
 
 int mco_project_range(mco_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t seed,
@@ -1206,9 +1325,9 @@ int mco_test_sample(mco_ctx *c, int process, int material, float e, uint64_t n, 
     for (uint64_t i = 0; i < n; ++i) {
         rng_t r;
         rng_init(&r, seed, i);
-        float ct, e2 = e;
+        float ct = 2.0f, e2 = e;
         if (process == MCO_PROC_COMPTON)
-            sample_compton(&r, e, &ct, &e2);
+            (void)compton_collision(c, &r, material, e, &ct, &e2);   /* null: ct stays 2 */
         else
             ct = sample_rayleigh(&r, e, c->rayl_b[material]);
         cos_out[i] = ct;
@@ -1225,6 +1344,14 @@ int mco_get_stats(mco_ctx *c, mco_stats *out) {
 }
 
 double mco_tally_scale(void) { return 1.0 / 1048576.0; }
+
+int mco_set_physics(mco_ctx *c, uint32_t flags) {
+    if (!c) return MCO_E_INVALID_ARG;
+    if (flags & ~(MCO_PHYS_INCOH_SF | MCO_PHYS_DOPPLER))
+        return fail(c, MCO_E_INVALID_ARG, "unknown physics flags");
+    c->phys = flags;
+    return MCO_OK;
+}
 
 int mco_set_estimator(mco_ctx *c, int mode, int split, double rr_kev) {
     if (!c) return MCO_E_INVALID_ARG;
@@ -1266,7 +1393,8 @@ int mco_pd_score_event(mco_ctx *c, float beta, uint64_t seed, uint64_t pid, int 
     if (rc) return rc;
     proj_t P;
     proj_setup(c, beta, &P);
-    pd_event(c, &P, seed, pid, n_prior, o, d, e_kev, material, process, scatter, &c->stats);
+    pd_event(c, &P, seed, pid, n_prior, n_prior, o, d, e_kev, material, process, scatter,
+             &c->stats);
     return MCO_OK;
 }
 

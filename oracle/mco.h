@@ -74,11 +74,17 @@ enum {
 /* geometry flags */
 #define MCO_NO_SCATTER 1u   /* every interaction absorbs (Beer-Lambert check) */
 
+/* binding effects (mco_set_physics); none by default (free electrons at rest:
+ * Klein-Nishina exactly) */
+#define MCO_PHYS_INCOH_SF 1u  /* S(x,Z) of eq. (1) by rejection (null collisions) */
+#define MCO_PHYS_DOPPLER 2u   /* Doppler broadening of the Compton energy        */
+
 /* processes for mco_test_sample */
 enum {
     MCO_PROC_SOURCE_ENERGY = 0, /* birth energy from the spectrum        */
     MCO_PROC_RAYLEIGH = 1,      /* Rayleigh polar angle                  */
-    MCO_PROC_COMPTON = 2,       /* Compton polar angle and energy        */
+    MCO_PROC_COMPTON = 2,       /* one Compton collision: polar cosine and
+                                   energy, cosine 2 for a null collision   */
     MCO_PROC_SOURCE_DIR = 3     /* cosine of the birth polar angle       */
 };
 
@@ -128,6 +134,7 @@ typedef struct mco_stats {
     uint64_t pd_scores;    /* point-detector pseudo-particles scored  */
     uint64_t pd_killed;    /* ... removed by Russian roulette         */
     uint64_t pd_steps;     /* march steps of their attenuation chords */
+    uint64_t null_collisions; /* Compton collisions rejected by S/Z     */
 } mco_stats;
 
 typedef struct mco_ctx mco_ctx;
@@ -184,6 +191,8 @@ int mco_debug_paths(mco_ctx *ctx, float angle_rad, uint64_t first, uint64_t m, u
  * estimator's scores (same expectation as the analog image); the primary
  * image and every photon's history are unchanged. */
 int mco_set_estimator(mco_ctx *ctx, int mode, int split, double rr_kev);
+/* binding effects: MCO_PHYS_INCOH_SF | MCO_PHYS_DOPPLER (see mco.c) */
+int mco_set_physics(mco_ctx *ctx, uint32_t flags);
 
 /* The point-detector scorer's angular pdf per unit scattering cosine
  * (eq. (4) for MCO_PROC_COMPTON, eq. (5) for MCO_PROC_RAYLEIGH) at energy
@@ -192,7 +201,8 @@ int mco_pd_pdf(mco_ctx *ctx, int process, int material, float e_kev, double lamb
                double *pdf, float *e_out);
 
 /* Adds to scatter[snv*snu] the point-detector scores of one scattering
- * event: photon pid of `seed`, its n_prior-th scattering (from 0), at point
+ * event: photon pid of `seed`, its n_prior-th collision (from 0: its
+ * scatterings, plus its null collisions under MCO_PHYS_INCOH_SF), at point
  * o with incoming direction d and energy e_kev in `material`, by `process`
  * (the estimator's split and roulette settings apply). */
 int mco_pd_score_event(mco_ctx *ctx, float angle_rad, uint64_t seed, uint64_t pid,

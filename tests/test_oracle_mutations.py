@@ -95,6 +95,28 @@ CASES = [
      "test_oracle_primary.py::test_primary_beer_lambert_box"),
     ("interp_neighbour", "o[p] = 0.5f * (a[p] + b[p]);", "o[p] = 0.5f * (a[p] + a[p]);",
      "test_oracle_primary.py::test_interp_angles_closed_form"),
+    # binding effects: S(x,Z) as null collisions, Doppler broadening
+    ("sf_power", "return 1.0 - 1.0 / (w2 * w2);", "return 1.0 - 1.0 / (w2 * w);",
+     "test_oracle_binding.py::test_sf_null_fraction_and_law"),
+    ("sf_momentum_transfer", "const double w = 1.0 + b * (0.5 * V * om);",
+     "const double w = 1.0 + b * (V * om);",
+     "test_oracle_binding.py::test_sf_null_fraction_and_law"),
+    ("null_collision_scatters", "if (!real) continue;", "if (!real && 0) continue;",
+     "test_oracle_binding.py::test_sf_primary_transmission"),
+    ("doppler_quadratic", "const double c2 = 1.0 - (t * tau) * tau;",
+     "const double c2 = 1.0 - (t * tau) * mu;",
+     "test_oracle_binding.py::test_doppler_momentum_profile"),
+    ("doppler_profile_power", "/ ((s2 * s2) * s2)", "/ (s2 * s2)",
+     "test_oracle_binding.py::test_doppler_momentum_profile"),
+    ("doppler_momentum_scale", "(cbrt((double)m[i].z_eff) / 0.885) / ALPHA_INV",
+     "(cbrt((double)m[i].z_eff) / 0.5) / ALPHA_INV",
+     "test_oracle_binding.py::test_doppler_momentum_profile"),
+    ("pd_sf_factor", "pdf *= incoh_sf(c->rayl_b[m], t * t, 1.0 - lam);", "pdf *= 1.0 + 0.0 * t;",
+     "test_oracle_binding.py::test_binding_pd_matches_analog"),
+    ("pd_doppler_missing",
+     "e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));",
+     "e2 = (float)((double)e2 + 0.0 * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));",
+     "test_oracle_binding.py::test_pd_doppler_vacuum_event"),
 ]
 
 
