@@ -373,9 +373,12 @@ mc_status mc_set_stats(mc_ctx *ctx, int enable);
 mc_status mc_get_stats(mc_ctx *ctx, mc_stats *out);
 
 /* Host-side cross-section tables exactly as the transport uses them:
- * fp32 mu/rho [cm^2/g] per material on E_j = 1 + j keV, arrays [n_mat][J],
- * and eta[J].  Pass NULL arrays to query J.  Needs the spectrum. */
-mc_status mc_get_tables(mc_ctx *ctx, int *J, float *pe, float *coh, float *inc, float *eta);
+ * fp32 mu/rho [cm^2/g] per material on E_j = 1 + j keV, arrays [n_mat][J]
+ * for the context's whole material set, and eta[J].  *J and *n_mat are
+ * always written; pass NULL arrays to query them first (each non-NULL array
+ * must hold n_mat * J, eta J, floats).  Needs the spectrum. */
+mc_status mc_get_tables(mc_ctx *ctx, int *J, int *n_mat, float *pe, float *coh, float *inc,
+                        float *eta);
 
 /* Device layout of the voxel object, chosen at the next mc_load_phantom.
  * AUTO: objects with <= 256 distinct (material, density) pairs are stored as

@@ -1418,10 +1418,12 @@ mc_status mc_set_estimator(mc_ctx *c, int mode, int split, double rr_kev) {
     return MC_OK;
 }
 
-mc_status mc_get_tables(mc_ctx *c, int *J, float *pe, float *coh, float *inc, float *eta) {
-    if (!c || !J) return MC_E_INVALID_ARG;
+mc_status mc_get_tables(mc_ctx *c, int *J, int *n_mat_out, float *pe, float *coh, float *inc,
+                        float *eta) {
+    if (!c || !J || !n_mat_out) return MC_E_INVALID_ARG;
     if (!c->have_spec) return fail(c, MC_E_STATE, "spectrum not set");
     const int n_mat = (int)c->mats.size();
+    *n_mat_out = n_mat;
     std::vector<Material> mm(n_mat);
     for (int i = 0; i < n_mat; ++i) mm[i] = {c->mats[i].z_eff, c->mats[i].z_over_a};
     const int Jn = table_length(c->e_max);

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -122,7 +123,7 @@ def load():
         "mc_test_sample": ([P, I, I, F, U64, U64, P, P], I),
         "mc_set_stats": ([P, I], I),
         "mc_get_stats": ([P, C.POINTER(mc_stats)], I),
-        "mc_get_tables": ([P, C.POINTER(I), P, P, P, P], I),
+        "mc_get_tables": ([P, C.POINTER(I), C.POINTER(I), P, P, P, P], I),
         "mc_set_layout": ([P, I], I),
         "mc_get_layout": ([P, C.POINTER(I), C.POINTER(I)], I),
         "mc_set_launch": ([P, I, I, I], I),
@@ -351,15 +352,20 @@ def mc_get_stats(ctx):
     return {n: getattr(s, n) for n, _ in mc_stats._fields_}
 
 
-def mc_get_tables(ctx, n_mat):
-    J = C.c_int()
-    _check(ctx, load().mc_get_tables(ctx, C.byref(J), None, None, None, None))
-    J = J.value
-    pe, coh, inc = (np.zeros((n_mat, J), np.float32) for _ in range(3))
+def mc_get_tables(ctx, n_mat=None):
+    """(pe, coh, inc, eta): [n_mat][J] tables of every material of the context
+    (the first n_mat rows when n_mat is given) and eta[J]."""
+    J, M = C.c_int(), C.c_int()
+    _check(ctx, load().mc_get_tables(ctx, C.byref(J), C.byref(M), None, None, None, None))
+    J, M = J.value, M.value
+    if n_mat is not None and not 1 <= n_mat <= M:
+        raise ValueError(f"the context has {M} materials, asked for {n_mat}")
+    pe, coh, inc = (np.zeros((M, J), np.float32) for _ in range(3))
     eta = np.zeros(J, np.float32)
-    _check(ctx, load().mc_get_tables(ctx, C.byref(C.c_int()), _np(pe), _np(coh), _np(inc),
-                                     _np(eta)))
-    return pe, coh, inc, eta
+    _check(ctx, load().mc_get_tables(ctx, C.byref(C.c_int()), C.byref(C.c_int()), _np(pe),
+                                     _np(coh), _np(inc), _np(eta)))
+    k = M if n_mat is None else n_mat
+    return pe[:k].copy(), coh[:k].copy(), inc[:k].copy(), eta
 
 
 def mc_set_layout(ctx, layout):
@@ -577,6 +583,10 @@ class Projector:
             self.ctx = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may be torn down before this
+        # object: the process's end releases the context then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -615,7 +625,7 @@ class Projector:
     def test_sample(self, process, material, e_kev, n, seed):
         return mc_test_sample(self.ctx, process, material, e_kev, n, seed)
 
-    def tables(self, n_mat):
+    def tables(self, n_mat=None):
         return mc_get_tables(self.ctx, n_mat)
 
     def set_estimator(self, mode, split=1, rr_kev=0.0):
