@@ -604,8 +604,15 @@ static double incoh_sf(double b, double V, double om) {
     return 1.0 - 1.0 / (w2 * w2);
 }
 
-/* one trial of the broadened ratio E'/E (pz = p0 / (m c)); 0 if rejected */
-static int doppler_trial(rng_t *r, double pz, double tau, double mu, double *ratio) {
+/* one trial of the broadened ratio E'/E (pz = p0 / (m c)), given tau, mu and
+ * the differences om = 1 - mu, omt = 1 - tau computed without cancellation;
+ * 0 if rejected.  The discriminant is written as
+ *   t ((1 - tau)^2 + tau (1 - mu) (2 - t tau (2 - (1 - mu)))),
+ * equal to (1 - t tau mu)^2 - (1 - t tau^2)(1 - t) but free of its
+ * cancellation near the forward direction, where the latter can round below
+ * zero for every draw. */
+static int doppler_trial(rng_t *r, double pz, double tau, double mu, double om, double omt,
+                         double *ratio) {
     const double v = 2.0 * (double)rng_u(r) - 1.0;
     const double u2 = (double)rng_u(r);
     const double a = fabs(v);
@@ -616,7 +623,7 @@ static int doppler_trial(rng_t *r, double pz, double tau, double mu, double *rat
     const double t = P * P;
     const double c1 = 1.0 - (t * tau) * mu;
     const double c2 = 1.0 - (t * tau) * tau;
-    const double disc = c1 * c1 - c2 * (1.0 - t);
+    const double disc = t * (omt * omt + tau * om * (2.0 - (t * tau) * (2.0 - om)));
     if (!(c2 > 0.0) || !(disc >= 0.0)) return 0;
     const double root = sqrt(disc);
     const double x = tau * ((P < 0.0 ? c1 - root : c1 + root) / c2);
@@ -625,14 +632,23 @@ static int doppler_trial(rng_t *r, double pz, double tau, double mu, double *rat
     return 1;
 }
 
-static double sample_doppler(rng_t *r, double pz, double tau, double mu) {
-    /* no momentum transfer (a point-detector direction along the photon's
-     * own): the line is not shifted, and no r < 1 solves the relation */
-    if (!(tau < 1.0)) return 1.0;
+#define DOPPLER_MAX_TRIALS 256
+
+/* E'/E at Compton ratio tau = 1 / ratio_kn and cosine 1 - om.  Without momentum
+ * transfer (a point-detector direction along the photon's own) the line is
+ * not shifted.  Each trial succeeds with probability above 0.2 (the draws
+ * with p_z < 0 always have a root), so the cap of 256 trials, after which the
+ * unbroadened ratio is returned, is reached with probability below 1e-24;
+ * it bounds the loop. */
+static double sample_doppler(rng_t *r, double pz, double ratio_kn, double om) {
+    const double tau = 1.0 / ratio_kn;
+    const double omt = (ratio_kn - 1.0) / ratio_kn;
+    if (!(tau < 1.0) || !(omt > 0.0)) return 1.0;
+    const double mu = 1.0 - om;
     double x;
-    while (!doppler_trial(r, pz, tau, mu, &x)) {
-    }
-    return x;
+    for (int k = 0; k < DOPPLER_MAX_TRIALS; ++k)
+        if (doppler_trial(r, pz, tau, mu, om, omt, &x)) return x;
+    return tau;
 }
 
 /* One Compton collision of the transport: Kahn's angle; with
@@ -648,8 +664,7 @@ static int compton_collision(const mco_ctx *c, rng_t *r, int m, float e, float *
     }
     *ct = (float)(1.0 - (x - 1.0) / alpha);
     if (c->phys & MCO_PHYS_DOPPLER)
-        *e2 = (float)((double)e * sample_doppler(r, c->pz_scale[m], 1.0 / x,
-                                                 1.0 - (x - 1.0) / alpha));
+        *e2 = (float)((double)e * sample_doppler(r, c->pz_scale[m], x, (x - 1.0) / alpha));
     else
         *e2 = (float)((double)e / x);
     return 1;
@@ -1003,7 +1018,7 @@ static void pd_event(const mco_ctx *c, const proj_t *P, uint64_t seed, uint64_t 
             rng_init_pseudo(&rd, seed, pid, (uint32_t)n, (uint32_t)i);
             const double alpha = (double)e / MEC2_KEV;
             const double ratio = 1.0 + alpha * (1.0 - lam);
-            e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));
+            e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], ratio, 1.0 - lam));
         }
         if (e2 < E_CUT_KEV) continue;       /* such a photon would be killed */
         const double eta = (double)lerp_tab(c->t_eta, c->J, e2);

@@ -103,8 +103,8 @@ CASES = [
      "test_oracle_binding.py::test_sf_null_fraction_and_law"),
     ("null_collision_scatters", "if (!real) continue;", "if (!real && 0) continue;",
      "test_oracle_binding.py::test_sf_primary_transmission"),
-    ("doppler_quadratic", "const double c2 = 1.0 - (t * tau) * tau;",
-     "const double c2 = 1.0 - (t * tau) * mu;",
+    ("doppler_discriminant", "tau * om * (2.0 - (t * tau) * (2.0 - om))",
+     "tau * om * (1.0 - (t * tau) * (2.0 - om))",
      "test_oracle_binding.py::test_doppler_momentum_profile"),
     ("doppler_profile_power", "/ ((s2 * s2) * s2)", "/ (s2 * s2)",
      "test_oracle_binding.py::test_doppler_momentum_profile"),
@@ -114,8 +114,8 @@ CASES = [
     ("pd_sf_factor", "pdf *= incoh_sf(c->rayl_b[m], t * t, 1.0 - lam);", "pdf *= 1.0 + 0.0 * t;",
      "test_oracle_binding.py::test_binding_pd_matches_analog"),
     ("pd_doppler_missing",
-     "e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));",
-     "e2 = (float)((double)e2 + 0.0 * sample_doppler(&rd, c->pz_scale[m], 1.0 / ratio, lam));",
+     "e2 = (float)((double)e * sample_doppler(&rd, c->pz_scale[m], ratio, 1.0 - lam));",
+     "e2 = (float)((double)e2 + 0.0 * sample_doppler(&rd, c->pz_scale[m], ratio, 1.0 - lam));",
      "test_oracle_binding.py::test_pd_doppler_vacuum_event"),
 ]
 
