@@ -110,6 +110,7 @@ typedef struct mc_stats {
     uint64_t pd_scores;      /* point-detector pseudo-particles scored            */
     uint64_t pd_killed;      /* ... removed by Russian roulette                   */
     uint64_t pd_steps;       /* march steps of their chords (included in `steps`) */
+    uint64_t null_collisions; /* Compton collisions rejected by S/Z (MC_PHYS_INCOH_SF) */
 } mc_stats;
 
 /* Create a context on HIP device `device`; allocates only small buffers.
@@ -186,6 +187,25 @@ mc_status mc_set_detector_response(mc_ctx *ctx, const float *eta, int n);
  * scores a heavy tail that this avoids. */
 #define MC_SCORE_POINT_MIXED 2
 mc_status mc_set_estimator(mc_ctx *ctx, int mode, int split, double rr_kev);
+
+/* Binding effects of eq. (1) and section II-A, off by default (free electrons
+ * at rest: Klein-Nishina exactly).  The paper takes S(x,Z) and the Compton
+ * profiles from tabulated atomic data; here both come from one parametric
+ * orbital model: every electron of a material in a 1s-like orbital of the
+ * Rayleigh form factor's screening radius r_Z = 0.885 a0 Z^(-1/3), so
+ * S(x,Z)/Z = 1 - (1 + b x^2)^-4 (b, x as for the form factor) and the
+ * profile J(p_z) ~ (1 + (p_z/p0)^2)^-3 with p0 = hbar / r_Z.
+ * MC_PHYS_INCOH_SF: a Compton collision is accepted with probability S/Z; a
+ * rejected one is a null collision that leaves the photon unchanged (the
+ * tables keep the Klein-Nishina cross section, so the effective cross
+ * section and the angular law are exact).  MC_PHYS_DOPPLER: the scattered
+ * energy is broadened by a p_z drawn from J (impulse approximation).  The
+ * point-detector scores include S/Z and broadened energies.  Applies to
+ * every transport entry point including batches; unknown bits:
+ * MC_E_INVALID_ARG. */
+#define MC_PHYS_INCOH_SF 1u
+#define MC_PHYS_DOPPLER 2u
+mc_status mc_set_physics(mc_ctx *ctx, uint32_t flags);
 
 /* Eq. (7), the primary image without Monte Carlo: d_out[nv*nu] (device fp32)
  * receives the expected primary tally per photon emitted into the cone, in
@@ -363,7 +383,8 @@ mc_status mc_debug_histories(mc_ctx *ctx, float angle_rad, uint64_t first, uint6
  * i using photon id i of `seed`.  SOURCE_ENERGY: e_out = birth energy.
  * SOURCE_DIR: cos_out = cosine of the birth direction to the central ray.
  * RAYLEIGH / COMPTON at e_keV in `material`: cos_out, e_out = outgoing
- * cosine and energy. */
+ * cosine and energy; COMPTON is one collision under the context's binding
+ * effects, a null collision giving cosine 2 and energy e_keV. */
 mc_status mc_test_sample(mc_ctx *ctx, int process, int material, float e_keV, uint64_t n,
                          uint64_t seed, float *cos_out, float *e_out);
 

@@ -90,6 +90,8 @@ struct KParams {
     const float *pe, *coh, *inc, *eta;
     int J, n_mat;
     const double *rayl_b;      // [n_mat] Rayleigh screening constants
+    const double *pz_scale;    // [n_mat] Compton-profile momentum scale / (m c)
+    uint32_t phys;             // binding effects: 1 S(x,Z) as null collisions, 2 Doppler
     const float *e_bin;        // [n_bins] bin energies
     const uint64_t *thr;       // [n_bins] cumulative thresholds on 32-bit draws
     const uint32_t *guide;     // [256] first bin whose threshold exceeds i * 2^24

@@ -129,6 +129,8 @@ struct mc_ctx {
 
     std::vector<mc_material> mats;
     std::vector<double> rayl_b;
+    std::vector<double> pz_scale;        // Compton-profile momentum scale / (m c)
+    uint32_t phys = 0;                   // MC_PHYS_* binding effects
 
     // voxel objects: [0] is the one of mc_load_phantom, more from mc_phantom_add
     std::vector<Phantom> phantoms = std::vector<Phantom>(1);
@@ -166,7 +168,7 @@ struct mc_ctx {
     const float *dp_ebin = nullptr;
     const uint64_t *dp_thr = nullptr;
     const uint32_t *dp_guide = nullptr;
-    const double *dp_rb = nullptr;
+    const double *dp_rb = nullptr, *dp_pz = nullptr;
 
     // control block: [0, kRing) photon counters, one per launch in turn so
     // launches queued on different streams never share one; then statistics
@@ -227,7 +229,11 @@ void set_materials(mc_ctx *c, const mc_material *m, int n) {
     ++c->generation;
     c->mats.assign(m, m + n);
     c->rayl_b.resize(n);
-    for (int i = 0; i < n; ++i) c->rayl_b[i] = rayleigh_b(m[i].z_eff);
+    c->pz_scale.resize(n);
+    for (int i = 0; i < n; ++i) {
+        c->rayl_b[i] = rayleigh_b(m[i].z_eff);
+        c->pz_scale[i] = compton_pz_scale(m[i].z_eff);
+    }
     c->tables_dirty = true;
 }
 
@@ -249,13 +255,13 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     build_tables(mm.data(), n_mat, J, c->eta_user.empty() ? nullptr : c->eta_user.data(),
                  (int)c->eta_user.size(), c->pe, c->coh, c->inc, c->eta);
     c->J = J;
-    // blob: rb[n_mat] f64 | kn[kKnTerms] f64 | coh series[kCohTerms] f64 |
+    // blob: rb[n_mat] f64 | pz[n_mat] f64 | kn[kKnTerms] f64 | coh series[kCohTerms] f64 |
     //       thr[n_bins] u64 | pe | coh | inc [n_mat*J] | eta[J] | e_bin[n_bins] |
     //       guide[256] u32
     const size_t nb = c->e_bin.size();
     const size_t tab = (size_t)n_mat * J;
     //       | bin_w[n_bins] f64 | bin_mu[n_bins][n_mat] f32 (the deterministic primary)
-    const size_t head = (size_t)(n_mat + kKnTerms + kCohTerms) * 8;
+    const size_t head = (size_t)(2 * n_mat + kKnTerms + kCohTerms) * 8;
     const size_t body = nb * 8 + (3 * tab + J + nb + 256) * 4;
     const size_t bins_off = ((head + body + 7) / 8) * 8;
     const size_t bytes = bins_off + nb * 8 + nb * n_mat * 4;
@@ -296,6 +302,7 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
         off += n;
     };
     put(c->rayl_b.data(), n_mat * 8);
+    put(c->pz_scale.data(), n_mat * 8);
     put(kn, sizeof kn);
     put(cohs, sizeof cohs);
     put(c->thr.data(), nb * 8);
@@ -322,8 +329,9 @@ mc_status refresh_tables(mc_ctx *c, bool may_alloc = true) {
     HIP_TRY(c, hipMemcpy(c->d_tables, blob.data(), bytes, hipMemcpyHostToDevice));
     unsigned char *b = (unsigned char *)c->d_tables;
     c->dp_rb = (const double *)b;
-    c->dp_kn = (const double *)b + n_mat;
-    c->dp_coh_series = (const double *)b + n_mat + kKnTerms;
+    c->dp_pz = (const double *)b + n_mat;
+    c->dp_kn = (const double *)b + 2 * n_mat;
+    c->dp_coh_series = (const double *)b + 2 * n_mat + kKnTerms;
     c->dp_thr = (const uint64_t *)(b + head);
     const float *f = (const float *)(b + head + nb * 8);
     c->dp_pe = f;
@@ -420,6 +428,8 @@ void common_params(mc_ctx *c, KParams &p) {
     p.J = c->J;
     p.n_mat = (int)c->mats.size();
     p.rayl_b = c->dp_rb;
+    p.pz_scale = c->dp_pz;
+    p.phys = c->phys;
     p.e_bin = c->dp_ebin;
     p.thr = c->dp_thr;
     p.guide = c->dp_guide;
@@ -1252,17 +1262,23 @@ mc_status mc_test_sample(mc_ctx *c, int process, int material, float e_kev, uint
     p.key0 = (uint32_t)seed;
     p.key1 = (uint32_t)(seed >> 32);
     if (n == 0) return MC_OK;
-    // outputs, then the per-material Rayleigh constants for the samplers
+    // outputs, then the per-material Rayleigh and Compton-profile constants for
+    // the samplers (with the context's binding effects)
     const size_t nm = c->mats.size();
     char *d = nullptr;
-    HIP_TRY(c, hipMalloc(&d, n * 2 * sizeof(float) + nm * sizeof(double)));
+    HIP_TRY(c, hipMalloc(&d, n * 2 * sizeof(float) + 2 * nm * sizeof(double)));
     hipStream_t s = c->stream;
     double *d_rb = (double *)(d + n * 2 * sizeof(float));
     float *d_cos = (float *)d, *d_e = (float *)d + n;
     hipError_t e = hipSuccess;
     if (angular) {
         e = hipMemcpyAsync(d_rb, c->rayl_b.data(), nm * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_rb + nm, c->pz_scale.data(), nm * sizeof(double),
+                               hipMemcpyHostToDevice, s);
         p.rayl_b = d_rb;
+        p.pz_scale = d_rb + nm;
+        p.phys = c->phys;
     }
     if (e == hipSuccess) e = launch_sample(p, process, material, e_kev, n, d_cos, d_e, s);
     if (e == hipSuccess && cos_out && process != MC_PROC_SOURCE_ENERGY)
@@ -1298,6 +1314,7 @@ mc_status mc_get_stats(mc_ctx *c, mc_stats *out) {
     out->pd_scores = h[11];
     out->pd_killed = h[12];
     out->pd_steps = h[13];
+    out->null_collisions = h[14];
     return MC_OK;
 }
 
@@ -1401,6 +1418,15 @@ mc_status mc_to_density_async(mc_ctx *c, const float *d_mu, uint64_t n, float th
                                      (double)c->mats[0].rho_default, step, d_ids, d_rho,
                                      (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "to density");
+    return MC_OK;
+}
+
+mc_status mc_set_physics(mc_ctx *c, uint32_t flags) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (flags & ~(uint32_t)(MC_PHYS_INCOH_SF | MC_PHYS_DOPPLER))
+        return fail(c, MC_E_INVALID_ARG, "unknown physics flags");
+    c->phys = flags;
+    ++c->generation;
     return MC_OK;
 }
 

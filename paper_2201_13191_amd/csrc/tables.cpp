@@ -137,6 +137,12 @@ double rayleigh_b(float z_eff) {
     return t * t;
 }
 
+double compton_pz_scale(float z_eff) {
+    // hbar / r_Z for the screening radius r_Z = 0.885 a0 Z^(-1/3): (a0 / r_Z)
+    // atomic units of momentum, one of which is m c / 137.035999084
+    return (std::cbrt((double)z_eff) / 0.885) / 137.035999084;
+}
+
 void savgol_weights(int window, int order, float *w) {
     // least-squares polynomial of degree `order` on offsets -h..h, value at 0:
     // row 0 of (A^T A)^-1 A^T with A[j][k] = j^k, solved by Gauss-Jordan in

@@ -27,6 +27,10 @@ void build_tables(const Material *mats, int n_mat, int J, const float *eta_user,
 // Screening constant b = (2 pi 0.885 a0 Z^(-1/3))^2 [A^2] of the Rayleigh sampler (fp64).
 double rayleigh_b(float z_eff);
 
+// Momentum scale p0 / (m c) of the 1s-like Compton profile of a material: the
+// orbital of the Rayleigh screening radius (fp64).
+double compton_pz_scale(float z_eff);
+
 // Spectrum bin thresholds on 32-bit draws: thr[k] = floor(W_k / W * 2^32) of the
 // cumulative weight, thr[n-1] = 2^32; the bin of draw x is the first k with x < thr[k].
 void spectrum_thresholds(const float *w, int n, std::vector<uint64_t> &thr);

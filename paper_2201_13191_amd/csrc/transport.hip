@@ -160,40 +160,6 @@ __device__ __forceinline__ void material_mu(const KParams &p, float e, float *mm
 }
 
 // ------------------------------------------------------------------ samplers
-// Kahn's rejection method for the Klein-Nishina polar angle: x = E/E' drawn
-// from one of two branches and accepted against the KN shape.  One trial
-// (three draws); on acceptance the scattered energy and polar cosine are set.
-__device__ __forceinline__ bool compton_trial(PhotonStream &s, float e, float &ct, float &e_out) {
-    const double a = (double)e / 510.99895;
-    const double top = 1.0 + 2.0 * a;
-    const double branch = top / (9.0 + 2.0 * a);
-    uint32_t w[3];
-    s.draw(w);
-    const double r1 = (double)unit_float(w[0]);
-    const double r2 = (double)unit_float(w[1]);
-    const double r3 = (double)unit_float(w[2]);
-    double x;
-    bool ok;
-    if (r1 <= branch) {
-        x = 1.0 + 2.0 * a * r2;
-        ok = r3 <= 4.0 * (1.0 / x - 1.0 / (x * x));
-    } else {
-        x = top / (1.0 + 2.0 * a * r2);
-        const double c = 1.0 - (x - 1.0) / a;
-        ok = r3 <= 0.5 * (c * c + 1.0 / x);
-    }
-    if (ok) {
-        e_out = (float)((double)e / x);
-        ct = (float)(1.0 - (x - 1.0) / a);
-    }
-    return ok;
-}
-
-__device__ void sample_compton(PhotonStream &s, float e, float &ct, float &e_out) {
-    while (!compton_trial(s, e, ct, e_out)) {
-    }
-}
-
 // Rayleigh polar angle: v = sin^2(theta/2)/lambda^2 inverted from the
 // (1 + b v)^-4 form-factor weight, accepted with (1 + cos^2)/2 evaluated on
 // the fp32 cosine.  One trial (two draws); the cosine is set either way.
@@ -220,6 +186,108 @@ __device__ float sample_rayleigh(S &s, float e, double b) {
     while (!rayleigh_trial(s, e, b, cf)) {
     }
     return cf;
+}
+
+// Kahn's rejection method for the Klein-Nishina polar angle: x = E / E_KN drawn
+// from one of two branches and accepted against the KN shape.  One trial
+// (three draws); false when rejected.
+__device__ __forceinline__ bool kahn_trial(PhotonStream &s, double a, double &x) {
+    const double top = 1.0 + 2.0 * a;
+    const double branch = top / (9.0 + 2.0 * a);
+    uint32_t w[3];
+    s.draw(w);
+    const double r1 = (double)unit_float(w[0]);
+    const double r2 = (double)unit_float(w[1]);
+    const double r3 = (double)unit_float(w[2]);
+    if (r1 <= branch) {
+        x = 1.0 + 2.0 * a * r2;
+        return r3 <= 4.0 * (1.0 / x - 1.0 / (x * x));
+    }
+    x = top / (1.0 + 2.0 * a * r2);
+    const double c = 1.0 - (x - 1.0) / a;
+    return r3 <= 0.5 * (c * c + 1.0 / x);
+}
+
+// ------------------------------------------------------------------ binding effects
+// Eq. (1)'s incoherent scattering function and the Doppler broadening of the
+// Compton line, from one orbital model: every electron in a 1s-like orbital of
+// the Rayleigh form factor's screening radius r_Z, so S/Z = 1 - (1 + b x^2)^-4
+// (b and x as for the form factor) and the Compton profile is
+// J(p_z) ~ (1 + (p_z / p0)^2)^-3 with p0 = hbar / r_Z.  S applies by rejection:
+// a rejected collision is a null collision that leaves the photon as it was,
+// and the tables stay Klein-Nishina, so the effective cross section and the
+// angular law are both exact.  Doppler: s = |p_z| / p0 from the envelope
+// (1 + s)^-2 by inversion (s = a / (1 - a)), accepted with
+// (1 + s)^2 / (M (1 + s^2)^3), M above the ratio's maximum; E'/E is the root in
+// (0, 1) of the impulse-approximation relation between p_z, the Compton ratio
+// tau = E_KN / E and the cosine, a draw without one drawn again (the draws with
+// p_z < 0 always have one when tau < 1).
+constexpr double kDopplerEnvelope = 1.3064;
+
+__device__ __forceinline__ double incoh_sf(double b, double V, double om) {
+    const double w = 1.0 + b * (0.5 * V * om);
+    const double w2 = w * w;
+    return 1.0 - 1.0 / (w2 * w2);
+}
+
+// E'/E at the Compton ratio ratio_kn = E / E_KN and 1 - cos = om.  The
+// discriminant is written as t ((1 - tau)^2 + tau om (2 - t tau (2 - om))),
+// free of the cancellation of (1 - t tau mu)^2 - (1 - t tau^2)(1 - t) near the
+// forward direction (where that form can round below zero for every draw).
+// Without momentum transfer the line is not shifted.  A trial succeeds with
+// probability above 0.2, so the cap of kDopplerMaxTrials trials (then the
+// unbroadened ratio) is reached with probability below 1e-24; it bounds the
+// loop.
+constexpr int kDopplerMaxTrials = 256;
+
+template <class S>
+__device__ double sample_doppler(S &s, double pz, double ratio_kn, double om) {
+    const double tau = 1.0 / ratio_kn;
+    const double omt = (ratio_kn - 1.0) / ratio_kn;
+    if (!(tau < 1.0) || !(omt > 0.0)) return 1.0;
+    const double mu = 1.0 - om;
+    for (int k = 0; k < kDopplerMaxTrials; ++k) {
+        uint32_t w[2];
+        s.draw(w);
+        const double v = 2.0 * (double)unit_float(w[0]) - 1.0;
+        const double u2 = (double)unit_float(w[1]);
+        const double a = fabs(v);
+        const double sm = a / (1.0 - a);
+        const double s2 = 1.0 + sm * sm;
+        if (!(u2 * kDopplerEnvelope <= ((1.0 + sm) * (1.0 + sm)) / ((s2 * s2) * s2))) continue;
+        const double P = (v < 0.0 ? -sm : sm) * pz;
+        const double t = P * P;
+        const double c1 = 1.0 - (t * tau) * mu;
+        const double c2 = 1.0 - (t * tau) * tau;
+        const double disc = t * (omt * omt + tau * om * (2.0 - (t * tau) * (2.0 - om)));
+        if (!(c2 > 0.0) || !(disc >= 0.0)) continue;
+        const double root = sqrt(disc);
+        const double x = tau * ((P < 0.0 ? c1 - root : c1 + root) / c2);
+        if (x > 0.0 && x < 1.0) return x;
+    }
+    return tau;
+}
+
+// One Compton collision with the binding effects p.phys asks for: Kahn's
+// angle, then (bit 0) acceptance with S/Z -- false for a null collision, the
+// outputs untouched -- and (bit 1) the broadened energy.
+__device__ bool compton_collision(PhotonStream &s, const KParams &p, int mat, float e, float &ct,
+                                  float &e_out) {
+    const double a = (double)e / 510.99895;
+    double x;
+    while (!kahn_trial(s, a, x)) {
+    }
+    if (p.phys & 1u) {
+        const double t = (double)e / 12.398419843320026;
+        const double u = (double)s.u();
+        if (!(u <= incoh_sf(p.rayl_b[mat], t * t, (x - 1.0) / a))) return false;
+    }
+    ct = (float)(1.0 - (x - 1.0) / a);
+    if (p.phys & 2u)
+        e_out = (float)((double)e * sample_doppler(s, p.pz_scale[mat], x, (x - 1.0) / a));
+    else
+        e_out = (float)((double)e / x);
+    return true;
 }
 
 // ------------------------------------------------------------------ point detector
@@ -342,7 +410,7 @@ __device__ __forceinline__ void cone_direction(const ProjFrame &F, PhotonStream 
 
 // ------------------------------------------------------------------ kernels
 enum : int { kStHist, kStSteps, kStFlights, kStPhoto, kStRayl, kStCompt, kStPrim, kStScat,
-             kStCut, kStCap, kStSkipped, kStPdScores, kStPdKilled, kStPdSteps, kStCount };
+             kStCut, kStCap, kStSkipped, kStPdScores, kStPdKilled, kStPdSteps, kStNull, kStCount };
 
 // optical-depth increments on the grid of 2^-32: fp64 sums of them are exact,
 // so a run of equal increments can be added at once
@@ -541,6 +609,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     float &dir_ct = last;
     uint32_t &phi_w = nsteps;
     int n_int = 0, mat = 0;
+    int n_coll = 0;     // scatterings and null collisions: point-detector counters
     unsigned long long st[kStCount] = {};
     uint32_t h_steps = 0;
     uint8_t h_first = 0;
@@ -582,6 +651,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
         for (int a = 0; a < 3; ++a) o[a] = F.S[a];
         tab_e = -1.0f;    // tables are rebuilt when the first flight starts
         n_int = 0;
+        n_coll = 0;
         alive = true;
         flying = false;
         if (DEBUG) {
@@ -643,22 +713,28 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
     // the photon scatters: polar angle by the process's sampler, then the
     // azimuth's and the next flight's draws; cut-offs end the history
     auto scatter = [&](bool rayleigh, int &end) __attribute__((always_inline)) {
-        float ct, e2;
+        float ct = 1.0f, e2 = e;
+        bool real = true;
         if (rayleigh) {
             ct = sample_rayleigh(rng, e, p.rayl_b[mat]);
             e2 = e;
             if (STATS) ++st[kStRayl];
             if (DEBUG && n_int == 0) h_first = 2;
         } else {
-            sample_compton(rng, e, ct, e2);
-            if (STATS) ++st[kStCompt];
-            if (DEBUG && n_int == 0) h_first = 3;
+            real = compton_collision(rng, p, mat, e, ct, e2);
+            if (STATS) {
+                st[kStCompt] += real ? 1ull : 0ull;
+                st[kStNull] += real ? 0ull : 1ull;
+            }
+            if (DEBUG && n_int == 0 && real) h_first = 3;
         }
         uint32_t w[2];
         rng.draw(w);
+        ts = (double)w[1];
+        ++n_coll;
+        if (!real) return;      // null collision: a new flight along the same line
         dir_ct = ct;
         phi_w = w[0];
-        ts = (double)w[1];
         turn = true;
         ++n_int;
         if (e2 < 1.0f) {
@@ -698,7 +774,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             // from the Rayleigh law (its own stream) and scores eta(E) / split
             // exp(-tau) where that line crosses the panel
             PseudoStream ps;
-            ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)n_int, (uint32_t)pd_i);
+            ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)n_coll, (uint32_t)pd_i);
             const float ct = sample_rayleigh(ps, e, p.rayl_b[mat]);
             double sphi, cphi;
             sincos(6.283185307179586 * (double)ps.u(), &sphi, &cphi);
@@ -735,7 +811,7 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             return true;
         }
         const uint4 w = philox4x32_10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32),
-                                                 (uint32_t)n_int, (uint32_t)pd_i + 1u),
+                                                 (uint32_t)n_coll, (uint32_t)pd_i + 1u),
                                       p.key0, p.key1);
         const float fu = unit_float(w.x) * (float)p.nu;
         const float fv = unit_float(w.y) * (float)p.nv;
@@ -764,6 +840,18 @@ __global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
             const double r = 1.0 / ratio;
             e2 = (float)((double)e / ratio);
             pdf = r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(p, alpha);
+            if (p.phys & 1u) {
+                // the law's deficit under S/Z is the null collisions' share
+                const double t = (double)e / 12.398419843320026;
+                pdf *= incoh_sf(p.rayl_b[mat], t * t, 1.0 - lam);
+            }
+            if (p.phys & 2u) {
+                // the broadened energy towards the point, from the
+                // pseudo-particle's own stream
+                PseudoStream ps;
+                ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)n_coll, (uint32_t)pd_i);
+                e2 = (float)((double)e * sample_doppler(ps, p.pz_scale[mat], ratio, 1.0 - lam));
+            }
         } else {
             // eq. (5): (1 + lambda^2) F^2 per unit cosine, energy unchanged
             const double t = (double)e / 12.398419843320026;
@@ -1341,8 +1429,8 @@ __global__ void sample_kernel(const KParams p, int process, int material, float 
         cos_out[i] = sample_rayleigh(s, e_kev, p.rayl_b[material]);
         if (e_out) e_out[i] = e_kev;
     } else {
-        float ct, e2;
-        sample_compton(s, e_kev, ct, e2);
+        float ct = 2.0f, e2 = e_kev;       // a null collision keeps cosine 2
+        (void)compton_collision(s, p, material, e_kev, ct, e2);
         cos_out[i] = ct;
         if (e_out) e_out[i] = e2;
     }

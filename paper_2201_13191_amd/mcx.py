@@ -34,7 +34,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
            "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
-           "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator",
+           "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator", "mc_set_physics",
            "mc_set_batch_launch", "mc_get_batch_info", "mc_autotune_batch",
            "mc_primary_expected_async", "mc_interp_angles_async", "mc_line_integrals_async",
            "mc_scatter_correct_async", "mc_fdk_async", "mc_histogram_async",
@@ -81,7 +81,7 @@ class mc_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "histories", "steps", "flights", "photo", "rayleigh", "compton",
         "primary_hits", "scatter_hits", "cutoff_kills", "cap_hits", "skipped_steps",
-        "pd_scores", "pd_killed", "pd_steps")]
+        "pd_scores", "pd_killed", "pd_steps", "null_collisions")]
 
 
 class MCXError(RuntimeError):
@@ -132,6 +132,7 @@ def load():
         "mc_project_batch": ([P, C.POINTER(mc_job), I, P, U64, C.c_uint32, P], I),
         "mc_project_batch_static": ([P, C.POINTER(mc_job), I, P, U64, P], I),
         "mc_set_estimator": ([P, I, I, C.c_double], I),
+        "mc_set_physics": ([P, C.c_uint32], I),
         "mc_set_batch_launch": ([P, I, I, I], I),
         "mc_primary_expected_async": ([P, F, I, P, P], I),
         "mc_line_integrals_async": ([P, P, U64, P, U64, P, P], I),
@@ -246,6 +247,12 @@ def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=N
 
 
 MC_SCORE_ANALOG, MC_SCORE_POINT, MC_SCORE_POINT_MIXED = 0, 1, 2
+MC_PHYS_INCOH_SF, MC_PHYS_DOPPLER = 1, 2
+
+
+def mc_set_physics(ctx, flags):
+    """Binding effects: MC_PHYS_INCOH_SF | MC_PHYS_DOPPLER (0: Klein-Nishina)."""
+    _check(ctx, load().mc_set_physics(ctx, int(flags)))
 
 
 def mc_set_estimator(ctx, mode, split=1, rr_kev=0.0):
@@ -630,6 +637,9 @@ class Projector:
 
     def set_estimator(self, mode, split=1, rr_kev=0.0):
         mc_set_estimator(self.ctx, mode, split, rr_kev)
+
+    def set_physics(self, flags):
+        mc_set_physics(self.ctx, flags)
 
     def set_layout(self, layout):
         mc_set_layout(self.ctx, layout)

@@ -220,6 +220,14 @@ def test_estimator_arguments(host_ctx):
             mcx.mc_set_estimator(host_ctx, *bad)
 
 
+def test_physics_arguments(host_ctx):
+    mcx.mc_set_physics(host_ctx, mcx.MC_PHYS_INCOH_SF | mcx.MC_PHYS_DOPPLER)
+    mcx.mc_set_physics(host_ctx, 0)
+    for bad in (4, 8, 0xFFFFFFFF):
+        with pytest.raises(mcx.MCXError):
+            mcx.mc_set_physics(host_ctx, bad)
+
+
 def test_static_batch_needs_device(host_ctx):
     import ctypes as C
     job = (mcx.mc_job * 1)(mcx.mc_job(0, 0.0, 1, 0, 0, 0))
