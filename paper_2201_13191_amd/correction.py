@@ -7,14 +7,17 @@ on synthetic data, built from the library's kernels.
                  collimator gives in the paper);
     convert    : a = -ln(I / I0), I0 the eq. (7) flat field (no object);
     loop       : FBP (FDK) -> Otsu threshold -> volume to density (water,
-                 density mu / (mu/rho)(E_eff)) -> Monte Carlo Ip, Is of that
-                 volume at every angle (or every other angle with the
-                 inter-projection interpolation) with optional Savitzky-Golay
-                 smoothing and cubic up-sampling of the scatter grid ->
+                 density mu / (mu/rho)(E_eff)) -> Ip of that volume from
+                 eq. (7) and Is from the Monte Carlo at every angle (or every
+                 other angle with the inter-projection interpolation), with
+                 optional Savitzky-Golay smoothing and cubic up-sampling of the
+                 scatter grid ->
                  c = a - ln(Ip / (Ip + Is)) (eq. (8)) -> FBP again;
     evaluate   : MSE, NCC (eq. (9)-(10)) against the reference reconstruction
-                 inside the object, and the CNR (eq. (11)) of a 14 x 14 pixel
-                 region of interest of the central slice against air.
+                 inside the object, the CNR (eq. (11)) of a 14 x 14 pixel region
+                 of interest of the central slice against air, and, to separate
+                 scatter's low-frequency error from noise, the rel-L2 of both
+                 volumes averaged over 5^3 voxels and the ratio of their means.
 
 Usage: python -m paper_2201_13191_amd.correction [--iterations 2 ...]
 """
@@ -27,6 +30,7 @@ import time
 
 import numpy as np
 import torch
+from scipy import ndimage
 
 from . import inputs, mcx, metrics
 
@@ -169,12 +173,20 @@ def _run(args, ctxs):
     roi = (c0, slice(c0 - 7, c0 + 7), slice(c0 - 7, c0 + 7))
     bg = (c0, slice(1, 15), slice(1, 15))
 
+    # the low-frequency error (scatter's cupping and shading) apart from the
+    # noise: both volumes averaged over 5^3 voxels
+    ref_s = ndimage.uniform_filter(ref_h, 5)
+
     def evaluate(v, tag):
         vh = v.cpu().numpy().astype(np.float64)
+        vs = ndimage.uniform_filter(vh, 5)
         r = dict(mse=metrics.mse(vh[obj], ref_h[obj]), ncc=metrics.ncc(vh[obj], ref_h[obj]),
-                 cnr=metrics.cnr(vh, roi, bg), rel_l2=metrics.rel_l2(vh[obj], ref_h[obj]))
+                 cnr=metrics.cnr(vh, roi, bg), rel_l2=metrics.rel_l2(vh[obj], ref_h[obj]),
+                 rel_l2_smooth=metrics.rel_l2(vs[obj], ref_s[obj]),
+                 mean_ratio=float(vh[obj].mean() / ref_h[obj].mean()))
         log(f"{tag}: MSE {r['mse']:.3e}, NCC {r['ncc']:.5f}, CNR {r['cnr']:.2f}, "
-            f"rel-L2 in object {r['rel_l2']:.4f}")
+            f"rel-L2 in object {r['rel_l2']:.4f} (5^3-smoothed {r['rel_l2_smooth']:.4f}), "
+            f"mean / reference {r['mean_ratio']:.4f}")
         return r
 
     res = {"reference": evaluate(ref, "reference (primary only)"),
@@ -196,18 +208,21 @@ def _run(args, ctxs):
         mcx.mc_to_density_async(truth.ctx, vol, thr, mu_rho, 1, args.density_step, d_ids,
                                 d_rho, stream)
         est.load_phantom(d_ids.cpu().numpy(), d_rho.cpu().numpy(), h)
+        # Ip of the estimate from eq. (7) (noise-free; the Monte Carlo primary
+        # of a low-count run has empty pixels behind dense paths), Is from the
+        # Monte Carlo, on every angle or on every other one and interpolated
+        ip = torch.empty_like(a)
+        ang = angles(n_ang)
+        for i in range(n_ang):
+            mcx.mc_primary_expected_async(est.ctx, ang[i], args.primary_sub, ip[i], stream)
         idx = range(0, n_ang, 2) if args.interpolate else range(n_ang)
-        ip, is_c = project(est, idx, n_ang, args.n_estimate, 1000 * (k + 1), stream)
+        _, is_c = project(est, idx, n_ang, args.n_estimate, 1000 * (k + 1), stream)
         if args.interpolate:
-            ip_f = torch.empty((n_ang,) + tuple(ip.shape[1:]), dtype=torch.float32,
-                               device="cuda")
             is_f = torch.empty((n_ang,) + tuple(is_c.shape[1:]), dtype=torch.float32,
                                device="cuda")
-            mcx.mc_interp_angles_async(est.ctx, ip.contiguous(), len(idx), ip[0].numel(), ip_f,
-                                       stream)
             mcx.mc_interp_angles_async(est.ctx, is_c.contiguous(), len(idx), is_c[0].numel(),
                                        is_f, stream)
-            ip, is_c = ip_f, is_f
+            is_c = is_f
         is_ = scatter_on_panel(est, is_c.contiguous(), args.savgol, stream)
         c = torch.empty_like(a)
         mcx.mc_scatter_correct_async(truth.ctx, a, ip.contiguous(), is_.contiguous(), c, stream)
@@ -236,6 +251,8 @@ def parse(argv=None):
     ap.add_argument("--n-estimate", type=int, default=5_000_000)
     ap.add_argument("--scatter-bin", type=int, default=4, help="panel pixels per scatter bin")
     ap.add_argument("--savgol", type=int, default=7, help="smoothing window (1: none)")
+    ap.add_argument("--primary-sub", type=int, default=2,
+                    help="sub-pixel rays per axis of the eq. (7) primary")
     ap.add_argument("--interpolate", action="store_true",
                     help="simulate every other angle, interpolate the rest")
     ap.add_argument("--iterations", type=int, default=2)

@@ -1,8 +1,9 @@
 """End-to-end run of the learned-part pipeline at reduced size: data from the
 batched launch, normalisation, training with the library's own kernels, and
 held-out evaluation against a high-count reference.  The network, trained
-briefly, must already beat the method without it (the low-count map
-up-sampled by cubic interpolation) on phantoms it has not seen."""
+briefly, must already beat the methods without it (the low-count map
+up-sampled by cubic interpolation, and that map smoothed by the Savitzky-Golay
+filter first, the paper's own post-processing) on phantoms it has not seen."""
 import math
 
 import pytest
@@ -30,4 +31,7 @@ def test_network_gain_small_training(tmp_path):
     assert all(math.isfinite(v) for v in out["losses"])
     assert 0 < out["reference_noise_rel"] < 1
     assert r["unet"]["debiased_mean"] < r["raw_cubic"]["debiased_mean"]
+    # and beats the paper's method without it (Savitzky-Golay + cubic up-sampling
+    # of the same input): measured 6.8 % against 11.6 % at this size
+    assert r["unet"]["debiased_mean"] < r["sg_cubic"]["debiased_mean"]
     assert out["plain_mc"]["histories_per_s"] > 1e8
