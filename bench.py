@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shape")
+    ap.add_argument("--launch", default="", metavar="BLOCK,BPC,EVENT_BATCH",
+                    help="this launch shape instead of the autotuner's")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pd-split", type=int, default=8,
                     help="point-detector pseudo-particles per scattering (0: skip that part)")
@@ -281,10 +283,16 @@ def main():
     # launch shape from the autotuner (untimed; every candidate is checked
     # bitwise against the first, the choice cached in the temp directory)
     tuning = None
-    if not args.no_autotune:
+    if args.launch:
+        blk, bpc, eb = (int(x) for x in args.launch.split(","))
+        g.set_launch(blk, bpc, eb)
+        log(f"launch shape set: block {blk}, blocks/CU {bpc}, event batch {eb}")
+    elif not args.no_autotune:
         import tempfile
         log("autotune")
-        tuning = mcx.mc_autotune(g.ctx, w["angle"], min(n, 100_000_000), w["seed"] + 7,
+        # tuned on the step itself: the photon count sets how much of a launch
+        # is its tail, so a shorter run can prefer another shape
+        tuning = mcx.mc_autotune(g.ctx, w["angle"], n, w["seed"] + 7,
                                  os.path.join(tempfile.gettempdir(), "mcx_tune.jsonl"))
         log(f"autotune: block {tuning['block']}, blocks/CU {tuning['blocks_per_cu']}, event batch "
             f"{tuning['event_batch']}, table layout {tuning['table_layout']}, "
@@ -459,9 +467,9 @@ def main():
             "photons_per_step": n,
             "step_mm": geo["step_mm"],
             "tallies": "int64 fixed point",
-            "launch": {k: tuning[k] for k in ("block", "blocks_per_cu", "event_batch",
-                                               "table_layout", "from_cache")} if tuning else
-                      "default",
+            "launch": ({k: tuning[k] for k in ("block", "blocks_per_cu", "event_batch",
+                                                "table_layout", "from_cache")} if tuning else
+                       args.launch or "default"),
         },
         "roofline": dict(roofline(st, gather_bytes, launch_s, args.workload, "transport_kernel"),
                          layout={0: "auto", 1: "palette-lane", 2: "palette-shared",

@@ -22,8 +22,11 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contr
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 # build-time knobs, e.g. MCX_DEFINES="MCX_PREFETCH=12 MCX_EDGE_PAD=13" (steps per
-# prefetch group; edge copies past the high faces, at least the group plus one)
+# prefetch group; edge copies past the high faces, at least the group plus one),
+# MCX_CELL_LOG (log2 of the uniform cells' edge in voxels), MCX_MIN_SKIP
+# (shortest run of uniform steps taken at once)
 HIP_FLAGS += [f"-D{d}" for d in os.environ.get("MCX_DEFINES", "").split()]
+CXX_FLAGS += [f"-D{d}" for d in os.environ.get("MCX_DEFINES", "").split()]
 
 SOURCES = [("transport.hip", "hip"), ("postproc.hip", "hip"), ("unet.hip", "hip"),
            ("recon.hip", "hip"),

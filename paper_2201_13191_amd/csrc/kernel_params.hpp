@@ -37,7 +37,10 @@ constexpr int kBrick = kBx * kBy * kBz;
 constexpr int kEdgePad = MCX_EDGE_PAD;
 // uniform-cell map: cubes of 2^kCellLog voxels per edge (4: measured faster
 // than 2, 8 or 16 on the 256^3 benchmark)
-constexpr int kCellLog = 2;
+#ifndef MCX_CELL_LOG
+#define MCX_CELL_LOG 2
+#endif
+constexpr int kCellLog = MCX_CELL_LOG;
 
 enum Layout : int {
     kPaletteLane = 0,    // byte = palette index; per-lane mu table of every palette entry

@@ -419,7 +419,10 @@ __device__ __forceinline__ double on_grid(double x) {
 }
 
 constexpr float kSkipMargin = 1.0f / 64.0f;   // voxels kept from a uniform region's faces
-constexpr uint32_t kMinSkip = 4;             // shortest run taken at once
+#ifndef MCX_MIN_SKIP
+#define MCX_MIN_SKIP 4
+#endif
+constexpr uint32_t kMinSkip = MCX_MIN_SKIP;  // shortest run taken at once
 
 
 #ifndef MCX_PREFETCH
@@ -507,7 +510,8 @@ __device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[
 // MODE: layout of the single object (ignored for batches, where each lane
 // follows the layout of its own job's object).  BATCH: run the job table.
 template <int MODE, bool BATCH, bool STATS, bool DEBUG, bool PD>
-__global__ void __launch_bounds__(256) transport_kernel(const KParams p) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PD || STATS || DEBUG) ? 1 : 3)))
+transport_kernel(const KParams p) {
     static_assert(!PD || (!BATCH && !DEBUG), "point-detector scoring: single projections only");
     // LDS: palette densities [256] | palette ids [256 bytes] (single object only) |
     // lane-private columns: mu per material [n_mat][bs] (fp32), then the

@@ -16,7 +16,7 @@ import sys
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmcx.so")
+LIB_PATH = os.environ.get("MCX_LIB", os.path.join(HERE, "libmcx.so"))   # MCX_LIB: a variant build
 
 MC_OK, MC_E_INVALID_ARG, MC_E_STATE, MC_E_OOM, MC_E_OVERFLOW, MC_E_DEVICE = 0, -1, -2, -3, -4, -6
 MC_NO_SCATTER = 1
@@ -589,10 +589,11 @@ class Projector:
             mc_destroy(self.ctx)
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may be torn down before this
-        # object: the process's end releases the context then
-        if sys.is_finalizing():
+        # object (and module globals cleared): the process's end releases the
+        # context then
+        if _finalizing():
             return
         try:
             self.close()
