@@ -12,10 +12,12 @@
 // conv3x3_kernel is an implicit GEMM: rows = pixels, columns = output
 // channels, reduction k = (tap, input channel).  Each lane's eight k values
 // of one MFMA operand are eight consecutive channels, a single 16-byte load
-// straight from global memory (L1/L2 serve the reuse).  One wave computes a
-// 32*WM x 32*WN tile with v_mfma_f32_32x32x16_bf16.  The same kernel computes
-// the input gradient of a convolution from its output gradient and the
-// flipped, transposed weights.
+// straight from global memory (L1/L2 serve the reuse), issued one k-step
+// ahead of the matrix products.  A 32*WM x 32*WN tile is computed with
+// v_mfma_f32_32x32x16_bf16 by one wave, or, for layers with few tiles, by 2 or
+// 4 waves over interleaved k-steps whose partial sums meet in LDS.  The same
+// kernel computes the input gradient of a convolution from its output
+// gradient and the flipped, transposed weights.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -38,16 +40,22 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-template <int WM, int WN>
+template <int WM, int WN, int KS>
 __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
+    // 4 waves: 4 / KS output tiles of 32*WM pixels x 32*WN channels, each
+    // computed by KS waves over interleaved k-steps and summed in LDS in a
+    // fixed order (deterministic)
+    extern __shared__ float s_part[];
+    constexpr int TPB = 4 / KS;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int tile = wave / KS, ks = wave - tile * KS;
     const int hw = a.h * a.w_;
     const int npix = a.n * hw;
-    const int px0 = (blockIdx.x * 4 + wave) * (32 * WM);
+    const int px0 = (blockIdx.x * TPB + tile) * (32 * WM);
     const int co0 = blockIdx.y * (32 * WN);
-    if (px0 >= npix) return;
-    const int kh = lane >> 5;          // which 8-channel half of the 16-k slice
+    const bool live = px0 < npix;       // no early return: the block meets at a barrier
+    const int kh = lane >> 5;           // which 8-channel half of the 16-k slice
     const int lr = lane & 31;
 
     int pn[WM], py[WM], pxx[WM];
@@ -70,41 +78,80 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
+    // k-step k: tap k / kc, channels 16 * (k % kc) .. +16
+    const int kc = a.cin >> 4;
+    const int K = 9 * kc;
     const size_t wk = (size_t)9 * a.cin;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const uint16_t *xrow[WM];
-        bool inb[WM];
+    auto load = [&](int k, bf16x8 (&av)[WM], bf16x8 (&bv)[WN]) __attribute__((always_inline)) {
+        const int tap = k / kc;
+        const int c0 = (k - tap * kc) << 4;
+        const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int yy = py[i] + dy, xx = pxx[i] + dx;
-            inb[i] = pv[i] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_;
-            xrow[i] = a.x + ((size_t)(pn[i] * a.h + (inb[i] ? yy : 0)) * a.w_ + (inb[i] ? xx : 0)) *
-                                a.ldx + a.xoff + kh * 8;
+            const bool inb = pv[i] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_;
+            if (inb) {
+                av[i] = *(const bf16x8 *)(a.x + ((size_t)(pn[i] * a.h + yy) * a.w_ + xx) * a.ldx +
+                                          a.xoff + c0 + kh * 8);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[i][e] = 0;
+            }
         }
-        for (int c0 = 0; c0 < a.cin; c0 += 16) {
-            bf16x8 av[WM], bv[WN];
 #pragma unroll
-            for (int i = 0; i < WM; ++i) {
-                if (inb[i]) {
-                    av[i] = *(const bf16x8 *)(xrow[i] + c0);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) av[i][e] = 0;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < WN; ++j) {
-                const int co = co0 + j * 32 + lr;
-                bv[j] = *(const bf16x8 *)(a.w + (size_t)co * wk + (size_t)tap * a.cin + c0 + kh * 8);
-            }
+        for (int j = 0; j < WN; ++j) {
+            const int co = co0 + j * 32 + lr;
+            bv[j] = *(const bf16x8 *)(a.w + (size_t)co * wk + (size_t)tap * a.cin + c0 + kh * 8);
+        }
+    };
+    if (live && ks < K) {
+        // one k-step of operands in flight ahead of the matrix products
+        bf16x8 av[WM], bv[WN], an[WM], bn[WN];
+        load(ks, av, bv);
+        for (int k = ks; k < K; k += KS) {
+            const bool more = k + KS < K;
+            if (more) load(k + KS, an, bn);
 #pragma unroll
             for (int i = 0; i < WM; ++i)
 #pragma unroll
                 for (int j = 0; j < WN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0,
+                                                                         0, 0);
+            if (more) {
+#pragma unroll
+                for (int i = 0; i < WM; ++i) av[i] = an[i];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) bv[j] = bn[j];
+            }
         }
     }
+    if constexpr (KS > 1) {
+        // partial tiles of waves ks = 1 .. KS-1, [tile][ks-1][register][lane]
+        constexpr int R = WM * WN * 16;
+        float *mine = s_part + ((size_t)(tile * (KS - 1) + (ks > 0 ? ks - 1 : 0)) * R) * 64;
+        if (ks > 0) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mine[((i * WN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+        }
+        __syncthreads();
+        if (ks > 0) return;
+        const float *base = s_part + (size_t)tile * (KS - 1) * R * 64;
+#pragma unroll 1
+        for (int q = 0; q < KS - 1; ++q) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        acc[i][j][r] += base[((size_t)q * R + (i * WN + j) * 16 + r) * 64 + lane];
+        }
+    }
+    if (!live) return;
     // epilogue: element r of a 32x32 accumulator is row 8*(r/4) + 4*(lane/32) + r%4,
     // column lane%32
 #pragma unroll
@@ -234,23 +281,57 @@ __global__ void wgrad_permute_kernel(const float *t, float *dw, int cout, int ci
 }
 
 // bias gradient: db[c] = sum over pixels of dy[p][c], per-block partials then a
-// fixed-order sum
-__global__ void colsum_kernel(const uint16_t *dy, int ldy, int yoff, int npix, int c, int chunk,
-                              float *partial) {
-    const int ch = blockIdx.y * blockDim.x + threadIdx.x;
-    if (ch >= c) return;
+// fixed-order sum.  A block sums one pixel range for 64 channels with 256
+// threads (4 interleaved pixel streams, four loads in flight per stream), the
+// streams added in LDS in a fixed order (deterministic).
+__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t *dy, int ldy, int yoff,
+                                                     int npix, int c, int chunk, float *partial) {
+    __shared__ float s_sum[4][64];
+    const int cl = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int ch = blockIdx.y * 64 + cl;
     const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
     float s = 0.0f;
-    for (int p = p0; p < p1; ++p) s += bf16_to_f32(dy[(size_t)p * ldy + yoff + ch]);
-    partial[(size_t)blockIdx.x * c + ch] = s;
+    if (ch < c) {
+        const uint16_t *col = dy + yoff + ch;
+        int p = p0 + sub;
+        for (; p + 12 < p1; p += 16) {
+            const float a0 = bf16_to_f32(col[(size_t)p * ldy]);
+            const float a1 = bf16_to_f32(col[(size_t)(p + 4) * ldy]);
+            const float a2 = bf16_to_f32(col[(size_t)(p + 8) * ldy]);
+            const float a3 = bf16_to_f32(col[(size_t)(p + 12) * ldy]);
+            s += ((a0 + a1) + a2) + a3;
+        }
+        for (; p < p1; p += 4) s += bf16_to_f32(col[(size_t)p * ldy]);
+    }
+    s_sum[sub][cl] = s;
+    __syncthreads();
+    if (sub == 0 && ch < c)
+        partial[(size_t)blockIdx.x * c + ch] = ((s_sum[0][cl] + s_sum[1][cl]) + s_sum[2][cl]) +
+                                               s_sum[3][cl];
 }
 
-__global__ void rowsum_kernel(const float *partial, int rows, int c, float *out) {
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= c) return;
+// the partial sums' rows added per channel, 4 interleaved row streams per
+// channel combined in a fixed order
+__global__ void __launch_bounds__(256) rowsum_kernel(const float *partial, int rows, int c,
+                                                     float *out) {
+    __shared__ float s_sum[4][64];
+    const int cl = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int ch = blockIdx.x * 64 + cl;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += partial[(size_t)r * c + ch];
-    out[ch] = s;
+    if (ch < c) {
+        int r = sub;
+        for (; r + 12 < rows; r += 16) {
+            const float a0 = partial[(size_t)r * c + ch];
+            const float a1 = partial[(size_t)(r + 4) * c + ch];
+            const float a2 = partial[(size_t)(r + 8) * c + ch];
+            const float a3 = partial[(size_t)(r + 12) * c + ch];
+            s += ((a0 + a1) + a2) + a3;
+        }
+        for (; r < rows; r += 4) s += partial[(size_t)r * c + ch];
+    }
+    s_sum[sub][cl] = s;
+    __syncthreads();
+    if (sub == 0 && ch < c) out[ch] = ((s_sum[0][cl] + s_sum[1][cl]) + s_sum[2][cl]) + s_sum[3][cl];
 }
 
 // W'[ci][tap][co] = W[co][8 - tap][ci] (bf16): weights of the input-gradient
@@ -398,16 +479,32 @@ __global__ void pack_channel_kernel(const float *in, int64_t npix, float scale, 
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t nn_conv3x3(const ConvArgs &a, hipStream_t s) {
+// Split of the reduction over the 4 waves of a block: layers with few output
+// tiles (the deep, narrow ones) give each tile 2 or 4 waves so that the chip
+// holds at least about two waves per SIMD.
+template <int WM, int WN>
+static hipError_t conv_launch(const ConvArgs &a, int tiles_co, hipStream_t s) {
     const int npix = a.n * a.h * a.w_;
-    if (a.cout <= 32) {
-        const dim3 grid((npix + 4 * 64 - 1) / (4 * 64), (a.cout + 31) / 32);
-        hipLaunchKernelGGL((conv3x3_kernel<2, 1>), grid, dim3(256), 0, s, a);
+    const int tiles_px = (npix + 32 * WM - 1) / (32 * WM);
+    const long tiles = (long)tiles_px * tiles_co;
+    const int K = 9 * (a.cin / 16);
+    constexpr size_t R = WM * WN * 16 * 64 * sizeof(float);   // one partial tile
+    if (tiles >= 2048 || K < 8) {
+        const dim3 grid((tiles_px + 3) / 4, tiles_co);
+        hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 1>), grid, dim3(256), 0, s, a);
+    } else if (tiles >= 1024 || K < 16) {
+        const dim3 grid((tiles_px + 1) / 2, tiles_co);
+        hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 2>), grid, dim3(256), 2 * R, s, a);
     } else {
-        const dim3 grid((npix + 4 * 64 - 1) / (4 * 64), (a.cout + 63) / 64);
-        hipLaunchKernelGGL((conv3x3_kernel<2, 2>), grid, dim3(256), 0, s, a);
+        const dim3 grid(tiles_px, tiles_co);
+        hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 4>), grid, dim3(256), 3 * R, s, a);
     }
     return hipGetLastError();
+}
+
+hipError_t nn_conv3x3(const ConvArgs &a, hipStream_t s) {
+    if (a.cout <= 32) return conv_launch<2, 1>(a, (a.cout + 31) / 32, s);
+    return conv_launch<2, 2>(a, (a.cout + 63) / 64, s);
 }
 
 hipError_t nn_wgrad(const WgradArgs &a, float *tmp, float *dw, hipStream_t s) {
@@ -424,9 +521,9 @@ hipError_t nn_wgrad(const WgradArgs &a, float *tmp, float *dw, hipStream_t s) {
 hipError_t nn_colsum(const uint16_t *dy, int ldy, int yoff, int npix, int c, float *partial,
                      int rows, float *out, hipStream_t s) {
     const int chunk = (npix + rows - 1) / rows;
-    hipLaunchKernelGGL(colsum_kernel, dim3(rows, (c + 63) / 64), dim3(64), 0, s, dy, ldy, yoff,
+    hipLaunchKernelGGL(colsum_kernel, dim3(rows, (c + 63) / 64), dim3(256), 0, s, dy, ldy, yoff,
                        npix, c, chunk, partial);
-    hipLaunchKernelGGL(rowsum_kernel, dim3((c + 63) / 64), dim3(64), 0, s, (const float *)partial,
+    hipLaunchKernelGGL(rowsum_kernel, dim3((c + 63) / 64), dim3(256), 0, s, (const float *)partial,
                        rows, c, out);
     return hipGetLastError();
 }

@@ -34,6 +34,8 @@ LAYERS = [
     ("h_a", 32, 16, True), ("h_b", 16, 1, False),
 ]
 INTERNAL_COUT = {"h_b": 16}
+# pixel ranges of the bias-gradient sums (blocks per 64 channels)
+BIAS_ROWS = 512
 
 
 def cout_alloc(c):
@@ -105,7 +107,7 @@ class UNet:
             coi = INTERNAL_COUT.get(name, co)
             ws = max(ws, (self._splits(name) + 1) * 9 * coi * ci)
         self.ws = torch.zeros(ws, **f32)
-        self.bias_ws = torch.zeros(64 * 256, **f32)
+        self.bias_ws = torch.zeros(BIAS_ROWS * 256, **f32)
 
     # ------------------------------------------------------------------ helpers
     def _splits(self, name):
@@ -220,7 +222,7 @@ class UNet:
                                       s, s, d["ci"], d["coi"], self._splits(name), self.ws,
                                       d["gw"], self.stream)
         mcx.mc_nn_bias_grad_async(self.ctx, gy, gy.shape[3], gyoff, n * s * s, d["coi"],
-                                  self.bias_ws, 64, d["gb"], self.stream)
+                                  self.bias_ws, BIAS_ROWS, d["gb"], self.stream)
         if gx is not None:
             mcx.mc_nn_conv3x3_async(self.ctx, gy, gy.shape[3], gyoff, d["wt"], None, gx,
                                     gx.shape[3], gxoff, n, s, s, d["coi"], d["ci"], relu=0,
@@ -325,3 +327,59 @@ class UNet:
     def load(self, path):
         with np.load(path, allow_pickle=False) as z:
             self.load_state({k: z[k] for k in z.files})
+
+
+def flops_per_sample(size=128):
+    """Multiply-adds x 2 of the 3x3 convolutions of one forward pass."""
+    f = 0
+    for name, ci, co, _ in LAYERS:
+        s = {"e1": 1, "e2": 2, "e3": 4, "b_": 8, "d3": 4, "d2": 2, "d1": 1, "h_": 0.5}[name[:2]]
+        f += 2 * 9 * ci * co * (size / s) ** 2
+    return f
+
+
+def _time(argv=None):
+    """Forward and training-step time of a batch on random data (no checkpoint)."""
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--no-train", action="store_true",
+                    help="forward passes only (one untimed, then --reps timed)")
+    args = ap.parse_args(argv)
+    g = mcx.Projector(0)
+    N, S = args.batch, args.size
+    net = UNet(g.ctx, N, S, seed=1)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    s = torch.rand((N, S, S), device="cuda", generator=gen)
+    p = torch.rand((N, S, S), device="cuda", generator=gen)
+    t = torch.rand((N, 2 * S, 2 * S), device="cuda", generator=gen)
+    net.set_input(s, p)
+    net.forward()
+    if not args.no_train:
+        net.train_step(s, p, t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.reps):
+        net.forward()
+    e1.record()
+    torch.cuda.synchronize()
+    fwd = e0.elapsed_time(e1) / args.reps
+    fl = flops_per_sample(S) * N
+    msg = (f"[unet] batch {N} at {S}^2: forward {fwd:.3f} ms ({fwd / N:.3f} ms per sample, "
+           f"{fl / (fwd * 1e-3) / 1e12:.1f} TFLOP/s of 3x3 convolutions)")
+    if not args.no_train:
+        e0.record()
+        for _ in range(args.reps):
+            net.train_step(s, p, t)
+        e1.record()
+        torch.cuda.synchronize()
+        msg += f", training step {e0.elapsed_time(e1) / args.reps:.3f} ms"
+    print(msg, flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    _time()

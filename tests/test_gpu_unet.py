@@ -40,9 +40,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+# The kernel splits each tile's reduction over 1, 2 or 4 waves by the layer's
+# tile count: the last two cases take the one- and two-wave paths, the others
+# the four-wave one (or two waves when the reduction is short).
 @pytest.mark.parametrize("n,s,cin,cout,ldx,xoff,relu", [
     (1, 8, 16, 32, 16, 0, 1), (2, 16, 32, 64, 48, 16, 1), (1, 12, 48, 128, 48, 0, 0),
-    (3, 9, 16, 16, 32, 16, 1), (1, 32, 384, 128, 384, 0, 1), (2, 5, 64, 1, 64, 0, 0)])
+    (3, 9, 16, 16, 32, 16, 1), (1, 32, 384, 128, 384, 0, 1), (2, 5, 64, 1, 64, 0, 0),
+    (2, 256, 16, 32, 32, 16, 1), (1, 256, 32, 32, 32, 0, 1)])
 def test_conv_forward(env, n, s, cin, cout, ldx, xoff, relu):
     torch, ctx = env
     say("conv", n, s, cin, cout, ldx, xoff, relu)
