@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the march-ceiling probe")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shape")
+    ap.add_argument("--layout", choices=["lane", "shared", "generic"], default="",
+                    help="voxel layout instead of the automatic choice")
     ap.add_argument("--launch", default="", metavar="BLOCK,BPC,EVENT_BATCH",
                     help="this launch shape instead of the autotuner's")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -268,6 +270,9 @@ def main():
     w = inputs.workload(args.workload)
     n = args.photons or w["n_photons"]
     g = mcx.Projector(0)
+    if args.layout:
+        g.set_layout({"lane": mcx.MC_LAYOUT_PALETTE_LANE, "shared": mcx.MC_LAYOUT_PALETTE_SHARED,
+                      "generic": mcx.MC_LAYOUT_GENERIC}[args.layout])
     g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
     g.set_geometry(**w["geometry"])
     g.set_spectrum(*w["spectrum"])

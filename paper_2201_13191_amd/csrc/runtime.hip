@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mcx.h"
@@ -384,9 +385,9 @@ VoxelGrid grid_of(const mc_ctx *c, const Phantom &ph) {
     G.cmax[1] = (float)(ph.ny - 1);
     G.cmax[2] = (float)(ph.nz - 1);
     G.inv_h = 1.0f / ph.h;
-    // runs of identical voxels are skipped where the lane keeps per-palette
-    // optical-depth increments
-    G.cells = G.layout == kPaletteLane ? ph.d_cells : nullptr;
+    // runs of identical voxels through uniform cells are taken at once in
+    // every layout
+    G.cells = ph.d_cells;
     G.ncx = ph.ncx;
     G.ncy = ph.ncy;
     const int nd[3] = {ph.nx, ph.ny, ph.nz};
@@ -659,8 +660,15 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     const int ncx = (nx + (1 << kCellLog) - 1) >> kCellLog;
     const int ncy = (ny + (1 << kCellLog) - 1) >> kCellLog;
     const int ncz = (nz + (1 << kCellLog) - 1) >> kCellLog;
-    std::vector<int16_t> cell_code;
-    if (palette_ok) cell_code.assign((size_t)ncx * ncy * ncz, -2);   // -2: no voxel seen yet
+    std::vector<int16_t> cell_code((size_t)ncx * ncy * ncz, -2);   // -2: no voxel seen yet
+    // generic objects: the (material, density) of each cell while it is uniform
+    // (state: 0 unseen, 1 uniform, 2 mixed), coded after the pass
+    std::vector<uint64_t> cell_key;
+    std::vector<uint8_t> cell_state;
+    if (!palette_ok) {
+        cell_key.assign(cell_code.size(), 0);
+        cell_state.assign(cell_code.size(), 0);
+    }
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
             const size_t row = ((size_t)z * ny + y) * nx;
@@ -673,6 +681,17 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                 if (!palette_ok) {
                     vox[off] = ids[row + x];
                     vr[off] = rho[row + x];
+                    uint32_t bits;
+                    std::memcpy(&bits, &rho[row + x], 4);
+                    const uint64_t key = ((uint64_t)ids[row + x] << 32) | bits;
+                    const size_t ci = ((size_t)(z >> kCellLog) * ncy + (y >> kCellLog)) * ncx +
+                                      (x >> kCellLog);
+                    if (cell_state[ci] == 0) {
+                        cell_state[ci] = 1;
+                        cell_key[ci] = key;
+                    } else if (cell_state[ci] == 1 && cell_key[ci] != key) {
+                        cell_state[ci] = 2;
+                    }
                     continue;
                 }
                 uint32_t bits;
@@ -711,8 +730,33 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
                     if (!palette_ok) vr[dst] = vr[src];
                 }
     }
+    // generic objects: the distinct values of their uniform cells, first
+    // appearance first, form a palette of at most 256 entries that only runs
+    // through uniform regions use (cells past the 256th value count as mixed)
+    if (!palette_ok) {
+        n_pal = 0;
+        std::unordered_map<uint64_t, int> code_of;
+        for (size_t i = 0; i < cell_code.size(); ++i) {
+            if (cell_state[i] != 1) {
+                cell_code[i] = -1;
+                continue;
+            }
+            auto it = code_of.find(cell_key[i]);
+            if (it == code_of.end()) {
+                if (n_pal == 256) {
+                    cell_code[i] = -1;
+                    continue;
+                }
+                it = code_of.emplace(cell_key[i], n_pal).first;
+                pal_id[n_pal] = (uint8_t)(cell_key[i] >> 32);
+                pal_rho_bits[n_pal] = (uint32_t)cell_key[i];
+                ++n_pal;
+            }
+            cell_code[i] = (int16_t)it->second;
+        }
+    }
     std::vector<uint16_t> cells;
-    if (palette_ok) cell_radii(ncx, ncy, ncz, cell_code, cells);
+    cell_radii(ncx, ncy, ncz, cell_code, cells);
     HIP_TRY(c, hipDeviceSynchronize());
     out.release();
     HIP_TRY(c, hipMalloc(&out.d_vox, padded));
@@ -720,23 +764,23 @@ mc_status build_phantom(mc_ctx *c, const uint8_t *ids, const float *rho, int nx,
     if (!palette_ok) {
         HIP_TRY(c, hipMalloc(&out.d_vrho, padded * sizeof(float)));
         HIP_TRY(c, hipMemcpy(out.d_vrho, vr.data(), padded * sizeof(float), hipMemcpyHostToDevice));
-    } else {
-        unsigned char pal[256 * 5] = {0};
-        std::memcpy(pal, pal_rho_bits, (size_t)n_pal * 4);
-        std::memcpy(pal + 256 * 4, pal_id, (size_t)n_pal);
-        HIP_TRY(c, hipMalloc(&out.d_pal, sizeof pal));
-        HIP_TRY(c, hipMemcpy(out.d_pal, pal, sizeof pal, hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMalloc(&out.d_cells, cells.size() * sizeof(uint16_t)));
-        HIP_TRY(c, hipMemcpy(out.d_cells, cells.data(), cells.size() * sizeof(uint16_t),
-                             hipMemcpyHostToDevice));
     }
+    // the palette (generic objects: of their uniform cells) and the cell map
+    unsigned char pal[256 * 5] = {0};
+    std::memcpy(pal, pal_rho_bits, (size_t)n_pal * 4);
+    std::memcpy(pal + 256 * 4, pal_id, (size_t)n_pal);
+    HIP_TRY(c, hipMalloc(&out.d_pal, sizeof pal));
+    HIP_TRY(c, hipMemcpy(out.d_pal, pal, sizeof pal, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMalloc(&out.d_cells, cells.size() * sizeof(uint16_t)));
+    HIP_TRY(c, hipMemcpy(out.d_cells, cells.data(), cells.size() * sizeof(uint16_t),
+                         hipMemcpyHostToDevice));
     out.ncx = ncx; out.ncy = ncy; out.ncz = ncz;
     out.nx = nx; out.ny = ny; out.nz = nz; out.h = h;
     out.nbx = nbx; out.nby = nby; out.nbz = nbz;
     out.edge_pad = edge_pad;
     out.max_id = max_id;
     out.generic = !palette_ok;
-    out.n_pal = palette_ok ? n_pal : 0;
+    out.n_pal = palette_ok ? n_pal : 0;     // generic: its cells' palette is not a voxel palette
     out.loaded = true;
     ++c->generation;
     return MC_OK;

@@ -268,22 +268,23 @@ __device__ double sample_doppler(S &s, double pz, double ratio_kn, double om) {
     return tau;
 }
 
-// One Compton collision with the binding effects p.phys asks for: Kahn's
-// angle, then (bit 0) acceptance with S/Z -- false for a null collision, the
-// outputs untouched -- and (bit 1) the broadened energy.
+// One Compton collision: Kahn's angle and, in the BIND variants, the binding
+// effects p.phys asks for: (bit 0) acceptance with S/Z -- false for a null
+// collision, the outputs untouched -- and (bit 1) the broadened energy.
+template <bool BIND>
 __device__ bool compton_collision(PhotonStream &s, const KParams &p, int mat, float e, float &ct,
                                   float &e_out) {
     const double a = (double)e / 510.99895;
     double x;
     while (!kahn_trial(s, a, x)) {
     }
-    if (p.phys & 1u) {
+    if (BIND && (p.phys & 1u)) {
         const double t = (double)e / 12.398419843320026;
         const double u = (double)s.u();
         if (!(u <= incoh_sf(p.rayl_b[mat], t * t, (x - 1.0) / a))) return false;
     }
     ct = (float)(1.0 - (x - 1.0) / a);
-    if (p.phys & 2u)
+    if (BIND && (p.phys & 2u))
         e_out = (float)((double)e * sample_doppler(s, p.pz_scale[mat], x, (x - 1.0) / a));
     else
         e_out = (float)((double)e / x);
@@ -509,7 +510,9 @@ __device__ __forceinline__ uint32_t cell_word(const VoxelGrid &g, const float q[
 
 // MODE: layout of the single object (ignored for batches, where each lane
 // follows the layout of its own job's object).  BATCH: run the job table.
-template <int MODE, bool BATCH, bool STATS, bool DEBUG, bool PD>
+// BIND: the binding-effect samplers are compiled in (launched when p.phys is
+// non-zero); without them the default path keeps its register budget.
+template <int MODE, bool BATCH, bool STATS, bool DEBUG, bool PD, bool BIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PD || STATS || DEBUG) ? 1 : 3)))
 transport_kernel(const KParams p) {
     static_assert(!PD || (!BATCH && !DEBUG), "point-detector scoring: single projections only");
@@ -692,8 +695,7 @@ transport_kernel(const KParams p) {
         nsteps = step_count(len, p.step);
         last = nsteps ? len - (float)(nsteps - 1u) * p.step : 0.0f;
         tau = 0.0;
-        const bool lane_pal = BATCH ? gr.layout == kPaletteLane : MODE == kPaletteLane;
-        cellw = lane_pal && gr.cells != nullptr ? cell_word(gr, q) : 0u;
+        cellw = gr.cells != nullptr ? cell_word(gr, q) : 0u;
         k = 0;
         flying = true;
     };
@@ -725,7 +727,7 @@ transport_kernel(const KParams p) {
             if (STATS) ++st[kStRayl];
             if (DEBUG && n_int == 0) h_first = 2;
         } else {
-            real = compton_collision(rng, p, mat, e, ct, e2);
+            real = compton_collision<BIND>(rng, p, mat, e, ct, e2);
             if (STATS) {
                 st[kStCompt] += real ? 1ull : 0ull;
                 st[kStNull] += real ? 0ull : 1ull;
@@ -735,7 +737,7 @@ transport_kernel(const KParams p) {
         uint32_t w[2];
         rng.draw(w);
         ts = (double)w[1];
-        ++n_coll;
+        if constexpr (BIND) ++n_coll;
         if (!real) return;      // null collision: a new flight along the same line
         dir_ct = ct;
         phi_w = w[0];
@@ -778,7 +780,8 @@ transport_kernel(const KParams p) {
             // from the Rayleigh law (its own stream) and scores eta(E) / split
             // exp(-tau) where that line crosses the panel
             PseudoStream ps;
-            ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)n_coll, (uint32_t)pd_i);
+            ps.reset_pseudo(pid, p.key0, p.key1, (uint32_t)(BIND ? n_coll : n_int),
+                            (uint32_t)pd_i);
             const float ct = sample_rayleigh(ps, e, p.rayl_b[mat]);
             double sphi, cphi;
             sincos(6.283185307179586 * (double)ps.u(), &sphi, &cphi);
@@ -815,7 +818,8 @@ transport_kernel(const KParams p) {
             return true;
         }
         const uint4 w = philox4x32_10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32),
-                                                 (uint32_t)n_coll, (uint32_t)pd_i + 1u),
+                                                 (uint32_t)(BIND ? n_coll : n_int),
+                                                 (uint32_t)pd_i + 1u),
                                       p.key0, p.key1);
         const float fu = unit_float(w.x) * (float)p.nu;
         const float fv = unit_float(w.y) * (float)p.nv;
@@ -844,12 +848,12 @@ transport_kernel(const KParams p) {
             const double r = 1.0 / ratio;
             e2 = (float)((double)e / ratio);
             pdf = r * r * ((r + ratio) - (1.0 - lam * lam)) / kn_norm(p, alpha);
-            if (p.phys & 1u) {
+            if (BIND && (p.phys & 1u)) {
                 // the law's deficit under S/Z is the null collisions' share
                 const double t = (double)e / 12.398419843320026;
                 pdf *= incoh_sf(p.rayl_b[mat], t * t, 1.0 - lam);
             }
-            if (p.phys & 2u) {
+            if (BIND && (p.phys & 2u)) {
                 // the broadened energy towards the point, from the
                 // pseudo-particle's own stream
                 PseudoStream ps;
@@ -1086,9 +1090,18 @@ transport_kernel(const KParams p) {
             if (!flying) continue;
             each_object([&](const VoxelGrid &gl) __attribute__((always_inline)) {
             const bool lane_pal = BATCH ? gl.layout == kPaletteLane : MODE == kPaletteLane;
-            const bool skips = lane_pal && gl.cells != nullptr;
+            const bool skips = gl.cells != nullptr;
             const int lay = BATCH ? gl.layout : MODE;
-            auto interact = [&](uint32_t c, double inc, float len) __attribute__((always_inline)) {
+            // the material of palette entry c: the object's palette (staged in
+            // LDS for a single palette object), or, for a generic object, the
+            // table of the values of its uniform cells
+            auto pal_material = [&](uint32_t c) __attribute__((always_inline)) -> int {
+                return (BATCH || lay == kGeneric) ? (int)dev(gl.pal_id)[c] : (int)s_pal_id[c];
+            };
+            // c: the voxel's code (generic: its material), or, with run = true,
+            // the palette entry of the uniform region the run went through
+            auto interact = [&](uint32_t c, double inc, float len, bool run)
+                __attribute__((always_inline)) {
                 // the point where the optical depth reaches tau* inside step k
                 const float si = (float)k * p.step + (float)((ts - tau) / inc * (double)len);
 #pragma unroll
@@ -1096,10 +1109,7 @@ transport_kernel(const KParams p) {
                     const float pin = o[a] + d[a] * tin;
                     o[a] = pin + d[a] * si;
                 }
-                if (lay == kGeneric)
-                    mat = (int)c;
-                else
-                    mat = BATCH ? (int)dev(gl.pal_id)[c] : (int)s_pal_id[c];
+                mat = (lay == kGeneric && !run) ? (int)c : pal_material(c);
                 event = 1;
                 flying = false;
             };
@@ -1130,7 +1140,19 @@ transport_kernel(const KParams p) {
                 cnt = (cnt < avail ? cnt : avail) & ~3u;
                 if (cnt >= kMinSkip) {
                     const uint32_t c = cell & 0xFFu;
-                    const double inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
+                    double inc;
+                    if (lane_pal) {
+                        inc = *(const double *)((const char *)inc_pal + __umul24(c, bs8));
+                    } else {
+                        // the per-step increment of the region's (density,
+                        // material), as the gathers below would compute it
+                        const bool lds_pal = !BATCH && MODE == kPaletteShared;
+                        const float rho = lds_pal ? s_pal_rho[c] : dev(gl.pal_rho)[c];
+                        const uint32_t id = lds_pal ? (uint32_t)s_pal_id[c]
+                                                    : (uint32_t)dev(gl.pal_id)[c];
+                        const float mu = rho * mm[id * bs];
+                        inc = __builtin_rint((double)mu * step32) * 2.3283064365386963e-10;
+                    }
                     const double tn = tau + (double)cnt * inc;
                     if (tn >= ts) {
                         // the first step of the run whose end reaches tau*:
@@ -1147,7 +1169,7 @@ transport_kernel(const KParams p) {
                         }
                         tau = tau + (double)j * inc;
                         k += j;
-                        interact(c, inc, p.step);
+                        interact(c, inc, p.step, true);
                     } else {
                         if (DEBUG) h_steps += cnt;
                         if (STATS) {
@@ -1279,13 +1301,13 @@ transport_kernel(const KParams p) {
                     r = r > 1.0 ? 1.0 : r;
                     const double inc_l = on_grid(inc_hit * r);
                     if (tau + inc_l >= ts) {
-                        interact(code_hit, inc_l, last);
+                        interact(code_hit, inc_l, last, false);
                     } else {
                         event = 2;
                         flying = false;
                     }
                 } else {
-                    interact(code_hit, inc_hit, p.step);
+                    interact(code_hit, inc_hit, p.step, false);
                 }
             }
             });
@@ -1434,7 +1456,7 @@ __global__ void sample_kernel(const KParams p, int process, int material, float 
         if (e_out) e_out[i] = e_kev;
     } else {
         float ct = 2.0f, e2 = e_kev;       // a null collision keeps cosine 2
-        (void)compton_collision(s, p, material, e_kev, ct, e2);
+        (void)compton_collision<true>(s, p, material, e_kev, ct, e2);
         cos_out[i] = ct;
         if (e_out) e_out[i] = e2;
     }
@@ -1452,26 +1474,32 @@ size_t batch_lds_bytes(const KParams &p, int max_lane_palette, int block) {
            (size_t)max_lane_palette * block * sizeof(double);
 }
 
+// the kernel with or without the binding-effect samplers, as p.phys asks
+template <int MODE, bool BATCH, bool STATS, bool DEBUG, bool PD>
+static void launch_k(const KParams &p, int grid, int block, size_t lds, hipStream_t stream) {
+    if (p.phys)
+        hipLaunchKernelGGL((transport_kernel<MODE, BATCH, STATS, DEBUG, PD, true>), dim3(grid),
+                           dim3(block), lds, stream, p);
+    else
+        hipLaunchKernelGGL((transport_kernel<MODE, BATCH, STATS, DEBUG, PD, false>), dim3(grid),
+                           dim3(block), lds, stream, p);
+}
+
 template <int MODE>
 static hipError_t launch_mode(const KParams &p, int grid, int block, bool stats, bool debug,
                               hipStream_t stream) {
     const size_t lds = transport_lds_bytes(p, MODE, block);
     const bool pd = p.pd_split > 0;   // point-detector scoring of the scatter image
     if (debug)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, false, true, false>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<MODE, false, false, true, false>(p, grid, block, lds, stream);
     else if (stats && pd)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false, true>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<MODE, false, true, false, true>(p, grid, block, lds, stream);
     else if (pd)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false, true>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<MODE, false, false, false, true>(p, grid, block, lds, stream);
     else if (stats)
-        hipLaunchKernelGGL((transport_kernel<MODE, false, true, false, false>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<MODE, false, true, false, false>(p, grid, block, lds, stream);
     else
-        hipLaunchKernelGGL((transport_kernel<MODE, false, false, false, false>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<MODE, false, false, false, false>(p, grid, block, lds, stream);
     return hipGetLastError();
 }
 
@@ -1487,11 +1515,9 @@ hipError_t launch_batch(const KParams &p, int max_lane_palette, int grid, int bl
                         hipStream_t stream) {
     const size_t lds = batch_lds_bytes(p, max_lane_palette, block);
     if (stats)
-        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, true, false, false>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<kPaletteLane, true, true, false, false>(p, grid, block, lds, stream);
     else
-        hipLaunchKernelGGL((transport_kernel<kPaletteLane, true, false, false, false>), dim3(grid),
-                           dim3(block), lds, stream, p);
+        launch_k<kPaletteLane, true, false, false, false>(p, grid, block, lds, stream);
     return hipGetLastError();
 }
 
@@ -1677,27 +1703,27 @@ hipError_t launch_sample(const KParams &p, int process, int material, float e_ke
     return hipGetLastError();
 }
 
-template <int MODE, bool BATCH>
-static int occupancy(int block, size_t lds, bool stats, bool pd) {
+template <int MODE, bool BATCH, bool STATS, bool PD>
+static int occ_k(int block, size_t lds, bool bind) {
     int nb = 0;
-    if constexpr (!BATCH) {
-        if (pd) {
-            if (stats)
-                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &nb, transport_kernel<MODE, false, true, false, true>, block, lds);
-            else
-                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &nb, transport_kernel<MODE, false, false, false, true>, block, lds);
-            return nb;
-        }
-    }
-    if (stats)
+    if (bind)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, transport_kernel<MODE, BATCH, true, false, false>, block, lds);
+            &nb, transport_kernel<MODE, BATCH, STATS, false, PD, true>, block, lds);
     else
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, transport_kernel<MODE, BATCH, false, false, false>, block, lds);
+            &nb, transport_kernel<MODE, BATCH, STATS, false, PD, false>, block, lds);
     return nb;
+}
+
+template <int MODE, bool BATCH>
+static int occupancy(int block, size_t lds, bool stats, bool pd, bool bind) {
+    if constexpr (!BATCH) {
+        if (pd)
+            return stats ? occ_k<MODE, false, true, true>(block, lds, bind)
+                         : occ_k<MODE, false, false, true>(block, lds, bind);
+    }
+    return stats ? occ_k<MODE, BATCH, true, false>(block, lds, bind)
+                 : occ_k<MODE, BATCH, false, false>(block, lds, bind);
 }
 
 int march_probe_blocks_per_cu(int layout, int block) {
@@ -1716,16 +1742,17 @@ int march_probe_blocks_per_cu(int layout, int block) {
 
 int transport_blocks_per_cu(const KParams &p, int layout, int block, bool stats) {
     const size_t lds = transport_lds_bytes(p, layout, block);
-    const bool pd = p.pd_split > 0;
-    int nb = layout == kPaletteLane     ? occupancy<kPaletteLane, false>(block, lds, stats, pd)
-             : layout == kPaletteShared ? occupancy<kPaletteShared, false>(block, lds, stats, pd)
-                                        : occupancy<kGeneric, false>(block, lds, stats, pd);
+    const bool pd = p.pd_split > 0, bind = p.phys != 0;
+    int nb = layout == kPaletteLane ? occupancy<kPaletteLane, false>(block, lds, stats, pd, bind)
+             : layout == kPaletteShared
+                 ? occupancy<kPaletteShared, false>(block, lds, stats, pd, bind)
+                 : occupancy<kGeneric, false>(block, lds, stats, pd, bind);
     return nb > 0 ? nb : 1;
 }
 
 int batch_blocks_per_cu(const KParams &p, int max_lane_palette, int block, bool stats) {
     const int nb = occupancy<kPaletteLane, true>(block, batch_lds_bytes(p, max_lane_palette, block),
-                                                stats, false);
+                                                stats, false, p.phys != 0);
     return nb > 0 ? nb : 1;
 }
 

@@ -308,3 +308,47 @@ def test_layouts_bitwise(gpu, shape, n_distinct):
     if n_distinct <= 32:
         assert seen == {mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED,
                         mcx.MC_LAYOUT_GENERIC}
+
+
+@pytest.mark.parametrize("n_values", [90, 700])
+def test_layouts_uniform_cells_bitwise(gpu, n_values):
+    """Runs through uniform regions in every layout: a uniform water slab next
+    to uniform 4-voxel cubes, each one (material, density) of n_values, with
+    scattered single voxels that make some cells mixed.  With 700 values the
+    generic layout's palette of uniform-cell values fills up (256 entries) and
+    the remaining uniform cells are taken step by step; images equal the
+    oracle's and the slab's runs are taken at once."""
+    rng = np.random.default_rng(n_values)
+    shape = (30, 27, 61)                      # z, y, x: not multiples of the cell
+    cz, cy, cx = [(s + 3) // 4 for s in shape]
+    keys = rng.integers(0, n_values, size=(cz, cy, cx))
+    keys = np.repeat(np.repeat(np.repeat(keys, 4, 0), 4, 1), 4, 2)[:shape[0], :shape[1], :shape[2]]
+    odd = rng.random(shape) < 0.01
+    keys = np.where(odd, rng.integers(0, n_values, size=shape), keys)
+    ids = (keys % 5).astype(np.uint8)
+    rho = (0.3 + 0.002 * keys).astype(np.float32)
+    ids[:, :, :24] = 1                         # the slab (first cell value seen)
+    rho[:, :, :24] = 1.0
+    geo = dict(sod_mm=400.0, sdd_mm=800.0, nu=40, nv=32, pu_mm=3.0, pv_mm=3.0, snu=10, snv=8,
+               step_mm=0.8, flags=0)
+    say("uniform cells", shape, n_values)
+    o = oracle.Oracle()
+    o.load_phantom(ids, rho, 1.0)
+    o.set_geometry(**geo)
+    o.set_spectrum(*inputs.kramers_spectrum(100, 1.0))
+    po, so = o.project(0.7, 200_000, 17, threads=8)
+    lays = [mcx.MC_LAYOUT_GENERIC] if n_values > 256 else \
+        [mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED, mcx.MC_LAYOUT_GENERIC]
+    for lay in lays:
+        g = mcx.Projector(0)
+        g.set_layout(lay)
+        g.load_phantom(ids, rho, 1.0)
+        g.set_geometry(**geo)
+        g.set_spectrum(*inputs.kramers_spectrum(100, 1.0))
+        g.stats(True)
+        pg, sg = g.project(0.7, 200_000, 17)
+        st = g.stats()
+        say("layout", lay, "skipped steps", st["skipped_steps"], "of", st["steps"])
+        assert st["skipped_steps"] > 0.05 * st["steps"], (lay, st)
+        assert np.array_equal(pg, po) and np.array_equal(sg, so), lay
+        g.close()
