@@ -56,6 +56,7 @@ typedef int32_t mc_status;
 #define MC_E_OOM (-3)         /* device or host allocation failed               */
 #define MC_E_OVERFLOW (-4)    /* n_photons * max eta * 2^20 could reach 2^63     */
 #define MC_E_DEVICE (-6)      /* HIP runtime error (message has its text)       */
+#define MC_E_CANCELLED (-7)   /* mc_cancel was on when a blocking call ended     */
 
 /* mc_geometry.flags */
 #define MC_NO_SCATTER 1u      /* every interaction absorbs: pure attenuation    */
@@ -262,6 +263,20 @@ mc_status mc_histogram_async(mc_ctx *ctx, const float *d_x, uint64_t n, float lo
 mc_status mc_to_density_async(mc_ctx *ctx, const float *d_mu, uint64_t n, float threshold,
                               float mu_rho, int material, float step, uint8_t *d_ids,
                               float *d_rho, void *stream);
+
+/* Cancellation, for callers that must stop a long projection or batch: with
+ * on = 1 every transport launch of the context that is running or queued stops
+ * taking photons (each wave reads the flag, kept in mapped host memory, every
+ * 64th scheduling round) and ends once the photons it holds are finished:
+ * each projection's images then hold photons 0 .. m-1 for some m, bitwise what
+ * a run of m photons gives, and nothing faults or hangs.  Launches made while
+ * the flag is on stop within their first rounds.
+ * mc_project then returns MC_E_CANCELLED (images written).  on = 0 clears the
+ * flag for later launches.  The only call that may run concurrently with
+ * other calls on the same context (from another host thread); an autotuner
+ * run during a cancellation reports candidates as rejected.  Host-only
+ * context: MC_E_STATE. */
+mc_status mc_cancel(mc_ctx *ctx, int on);
 
 /* One projection, blocking: simulates photons 0 .. n_photons-1 (emitted into
  * the cone circumscribing the panel) with Philox key `seed`, and writes the

@@ -111,6 +111,7 @@ struct KParams {
     unsigned long long *prim, *scat;     // int64 tallies (two's complement adds)
     unsigned long long *counter;         // next photon index (relative to first)
     unsigned long long *stats;           // mc_stats layout, or null
+    const int *cancel;                   // host-memory cancellation flag (mapped), or null
     // batch: jobs run in order, each wave moving to the next job when the
     // current one has no photons left
     const JobDesc *jobs;

@@ -175,6 +175,9 @@ struct mc_ctx {
     // launches queued on different streams never share one; then statistics
     unsigned long long *d_ctl = nullptr;
     unsigned launches = 0;
+    // cancellation flag in mapped host memory (mc_cancel), its device address
+    int *h_cancel = nullptr;
+    const int *d_cancel = nullptr;
     bool stats_on = false;
 
     // staging for mc_project
@@ -442,6 +445,7 @@ void common_params(mc_ctx *c, KParams &p) {
     p.flags = g.flags;
     p.event_batch = c->event_batch > 0 ? c->event_batch : kDefaultEventBatch;
     p.stats = c->d_ctl + kRing;
+    p.cancel = c->d_cancel;
     p.kn_series = c->dp_kn;
     p.coh_series = c->dp_coh_series;
     p.pd_split = 0;      // single projections turn the point detector on (prepare)
@@ -528,8 +532,16 @@ mc_status mc_create(mc_ctx **out, int device) {
     if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess ||
         hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&c->d_ctl, kCtlWords * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->d_ctl, 0, kCtlWords * sizeof(unsigned long long)) != hipSuccess)
+        hipMemset(c->d_ctl, 0, kCtlWords * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_cancel, sizeof(int),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         rc = MC_E_DEVICE;
+    if (!rc) {
+        *c->h_cancel = 0;
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, c->h_cancel, 0) != hipSuccess) rc = MC_E_DEVICE;
+        c->d_cancel = (const int *)dp;
+    }
     if (rc) {
         mc_destroy(c);
         return rc;
@@ -561,6 +573,7 @@ void mc_destroy(mc_ctx *c) {
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->d_img) (void)hipFree(c->d_img);
     if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->h_cancel) (void)hipHostFree(c->h_cancel);
     delete c;
 }
 
@@ -1133,6 +1146,15 @@ mc_status mc_project(mc_ctx *c, float beta, uint64_t n, uint64_t seed, int64_t *
     HIP_TRY(c, hipMemcpyAsync(scat, c->d_img + np, ns * sizeof(int64_t), hipMemcpyDeviceToHost,
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (__atomic_load_n(c->h_cancel, __ATOMIC_SEQ_CST))
+        return fail(c, MC_E_CANCELLED, "cancelled: the images hold the photons taken before it");
+    return MC_OK;
+}
+
+mc_status mc_cancel(mc_ctx *c, int on) {
+    if (!c) return MC_E_INVALID_ARG;
+    if (!c->h_cancel) return fail(c, MC_E_STATE, "host-only context");
+    __atomic_store_n(c->h_cancel, on ? 1 : 0, __ATOMIC_SEQ_CST);
     return MC_OK;
 }
 

@@ -597,6 +597,7 @@ transport_kernel(const KParams p) {
     };
 
     bool alive = false, flying = false, exhausted = false;
+    uint32_t rounds = 0;     // scheduling rounds of this wave (cancellation checks)
     PhotonStream rng;
     uint64_t pid = 0;
     float e = 0.0f;
@@ -995,6 +996,14 @@ transport_kernel(const KParams p) {
             alive = false;
         }
         // ---- 3. refill dead lanes: one atomic per wave (per job touched)
+        // A cancellation request (a flag in host memory, read every 64th round
+        // of a wave) ends the launch's intake: the photons in flight finish.
+        if (!exhausted && p.cancel != nullptr && (++rounds & 63u) == 0u) {
+            int flag = 0;
+            if (lane == 0)
+                flag = __hip_atomic_load(p.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (__builtin_amdgcn_readfirstlane(flag) != 0) exhausted = true;
+        }
         if (!exhausted) {
             unsigned long long dead = __ballot(!alive);
             while (dead) {

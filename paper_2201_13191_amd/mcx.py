@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MCX_LIB", os.path.join(HERE, "libmcx.so"))   # MCX_LIB: a variant build
 
 MC_OK, MC_E_INVALID_ARG, MC_E_STATE, MC_E_OOM, MC_E_OVERFLOW, MC_E_DEVICE = 0, -1, -2, -3, -4, -6
+MC_E_CANCELLED = -7
 MC_NO_SCATTER = 1
 MC_PROC_SOURCE_ENERGY, MC_PROC_RAYLEIGH, MC_PROC_COMPTON, MC_PROC_SOURCE_DIR = 0, 1, 2, 3
 MC_END_PRIMARY, MC_END_SCATTER, MC_END_MISSED, MC_END_PHOTO, MC_END_CUTOFF, MC_END_CAP = range(6)
@@ -34,7 +35,7 @@ EXPORTS = ["mc_create", "mc_destroy", "mc_last_error", "mc_set_materials", "mc_l
            "mc_nn_pool2_async", "mc_nn_upsample2_async", "mc_nn_mse_async", "mc_nn_adam_async",
            "mc_nn_relu_mask_async", "mc_nn_cast_bf16_async", "mc_nn_pack_channel_async",
            "mc_march_probe_async", "mc_cell_map", "mc_flip2d_async", "mc_atomic_probe_async",
-           "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator", "mc_set_physics",
+           "mc_make_kramers", "mc_project_batch_static", "mc_set_estimator", "mc_set_physics", "mc_cancel",
            "mc_set_batch_launch", "mc_get_batch_info", "mc_autotune_batch",
            "mc_primary_expected_async", "mc_interp_angles_async", "mc_line_integrals_async",
            "mc_scatter_correct_async", "mc_fdk_async", "mc_histogram_async",
@@ -133,6 +134,7 @@ def load():
         "mc_project_batch_static": ([P, C.POINTER(mc_job), I, P, U64, P], I),
         "mc_set_estimator": ([P, I, I, C.c_double], I),
         "mc_set_physics": ([P, C.c_uint32], I),
+        "mc_cancel": ([P, I], I),
         "mc_set_batch_launch": ([P, I, I, I], I),
         "mc_primary_expected_async": ([P, F, I, P, P], I),
         "mc_line_integrals_async": ([P, P, U64, P, U64, P, P], I),
@@ -248,6 +250,12 @@ def mc_project_batch(ctx, jobs, d_out, out_elems, flags=MC_BATCH_GRAPH, stream=N
 
 MC_SCORE_ANALOG, MC_SCORE_POINT, MC_SCORE_POINT_MIXED = 0, 1, 2
 MC_PHYS_INCOH_SF, MC_PHYS_DOPPLER = 1, 2
+
+
+def mc_cancel(ctx, on=True):
+    """Stop (on) the context's running and queued transport launches, or clear
+    the request (off); safe to call from another thread during a call."""
+    _check(ctx, load().mc_cancel(ctx, 1 if on else 0))
 
 
 def mc_set_physics(ctx, flags):
@@ -641,6 +649,9 @@ class Projector:
 
     def set_physics(self, flags):
         mc_set_physics(self.ctx, flags)
+
+    def cancel(self, on=True):
+        mc_cancel(self.ctx, on)
 
     def set_layout(self, layout):
         mc_set_layout(self.ctx, layout)

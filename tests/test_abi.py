@@ -236,3 +236,9 @@ def test_static_batch_needs_device(host_ctx):
     rc = mcx.load().mc_project_batch_static(host_ctx, job, mcx.MC_STATIC_MAX_JOBS + 1,
                                             C.c_void_p(16), 1, None)
     assert rc == mcx.MC_E_INVALID_ARG
+
+
+def test_cancel_needs_device(host_ctx):
+    with pytest.raises(mcx.MCXError) as e:
+        mcx.mc_cancel(host_ctx, True)
+    assert e.value.code == mcx.MC_E_STATE
