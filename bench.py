@@ -231,9 +231,10 @@ def main():
     ap.add_argument("--launch", default="", metavar="BLOCK,BPC,EVENT_BATCH",
                     help="this launch shape instead of the autotuner's")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--pd-split", type=int, default=8,
+    ap.add_argument("--pd-split", type=int, default=20,
                     help="point-detector pseudo-particles per scattering (0: skip that part)")
-    ap.add_argument("--pd-rr", type=float, default=0.0, help="roulette threshold, keV")
+    ap.add_argument("--pd-rr", type=float, default=1.0,
+                    help="roulette threshold, keV (0: no roulette)")
     ap.add_argument("--pd-point-only", dest="pd_mixed", action="store_false",
                     help="the point detector also for Rayleigh events (default: mixed, Rayleigh "
                          "pseudo-particles along their own law)")
