@@ -12,7 +12,7 @@
 // conv3x3_kernel is an implicit GEMM: rows = pixels, columns = output
 // channels, reduction k = (tap, input channel).  Each lane's eight k values
 // of one MFMA operand are eight consecutive channels, a single 16-byte load
-// straight from global memory (L1/L2 serve the reuse), issued one k-step
+// straight from global memory (L1/L2 serve the reuse), issued a few k-steps
 // ahead of the matrix products.  A 32*WM x 32*WN tile is computed with
 // v_mfma_f32_32x32x16_bf16 by one wave, or, for layers with few tiles, by 2 or
 // 4 waves over interleaved k-steps whose partial sums meet in LDS.  The same
@@ -38,6 +38,20 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     const uint32_t u = __float_as_uint(f);
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+#ifndef MCX_CONV_DEPTH
+#define MCX_CONV_DEPTH 3
+#endif
+constexpr int kConvDepth = MCX_CONV_DEPTH;   // k-steps of operands in flight
+constexpr int kEpStride = 40;   // floats per staged row: the two row groups of a
+                                // store fall on disjoint LDS banks
+
+// the wave's LDS writes made visible to all its lanes
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int WM, int WN, int KS>
@@ -82,21 +96,22 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
     const int kc = a.cin >> 4;
     const int K = 9 * kc;
     const size_t wk = (size_t)9 * a.cin;
-    auto load = [&](int k, bf16x8 (&av)[WM], bf16x8 (&bv)[WN]) __attribute__((always_inline)) {
+    // Loads are issued without branches, so that the compiler can count them
+    // in flight: a k-step past the end reloads the last one (its products are
+    // skipped), and a tap outside the image reads pixel 0 of the tensor and
+    // is masked to zero when used.
+    auto load = [&](int k, bf16x8 (&av)[WM], bf16x8 (&bv)[WN], bool (&ok)[WM])
+        __attribute__((always_inline)) {
+        k = k < K ? k : K - 1;
         const int tap = k / kc;
         const int c0 = (k - tap * kc) << 4;
         const int dy = tap / 3 - 1, dx = tap - 3 * (tap / 3) - 1;
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
             const int yy = py[i] + dy, xx = pxx[i] + dx;
-            const bool inb = pv[i] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_;
-            if (inb) {
-                av[i] = *(const bf16x8 *)(a.x + ((size_t)(pn[i] * a.h + yy) * a.w_ + xx) * a.ldx +
-                                          a.xoff + c0 + kh * 8);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) av[i][e] = 0;
-            }
+            ok[i] = pv[i] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w_;
+            const size_t pix = ok[i] ? (size_t)(pn[i] * a.h + yy) * a.w_ + xx : 0;
+            av[i] = *(const bf16x8 *)(a.x + pix * a.ldx + a.xoff + c0 + kh * 8);
         }
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
@@ -105,23 +120,29 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
         }
     };
     if (live && ks < K) {
-        // one k-step of operands in flight ahead of the matrix products
-        bf16x8 av[WM], bv[WN], an[WM], bn[WN];
-        load(ks, av, bv);
-        for (int k = ks; k < K; k += KS) {
-            const bool more = k + KS < K;
-            if (more) load(k + KS, an, bn);
+        // kConvDepth k-steps of operands in flight ahead of the matrix
+        // products: a ring of register buffers, each refilled right after its
+        // products are issued
+        bf16x8 av[kConvDepth][WM], bv[kConvDepth][WN];
+        bool ok[kConvDepth][WM];
+        const bf16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-            for (int i = 0; i < WM; ++i)
+        for (int s = 0; s < kConvDepth; ++s) load(ks + s * KS, av[s], bv[s], ok[s]);
+        for (int k = ks; k < K; k += kConvDepth * KS) {
 #pragma unroll
-                for (int j = 0; j < WN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0,
-                                                                         0, 0);
-            if (more) {
+            for (int s = 0; s < kConvDepth; ++s) {
+                // a step past the end multiplies zeros (no branch: the
+                // accumulators stay in the matrix registers)
+                const int kk = k + s * KS;
 #pragma unroll
-                for (int i = 0; i < WM; ++i) av[i] = an[i];
+                for (int i = 0; i < WM; ++i) {
+                    const bf16x8 x = (ok[s][i] && kk < K) ? av[s][i] : zero;
 #pragma unroll
-                for (int j = 0; j < WN; ++j) bv[j] = bn[j];
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, bv[s][j], acc[i][j],
+                                                                             0, 0, 0);
+                }
+                load(kk + kConvDepth * KS, av[s], bv[s], ok[s]);
             }
         }
     }
@@ -153,12 +174,105 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
     }
     if (!live) return;
     // epilogue: element r of a 32x32 accumulator is row 8*(r/4) + 4*(lane/32) + r%4,
-    // column lane%32
+    // column lane%32.  When the channel count is a multiple of 16 and the
+    // rows are 16-byte aligned, a slab of 32 channels is turned around in LDS
+    // (row = pixel), so that each lane finishes 16 consecutive channels of
+    // one pixel with 16-byte loads and stores; otherwise element by element.
+    const bool vec_ok =
+        (a.y == nullptr || (((a.ldy | a.yoff) & 7) == 0 && ((uintptr_t)a.y & 15) == 0)) &&
+        (a.mask == nullptr || (((a.ldm | a.moff) & 7) == 0 && ((uintptr_t)a.mask & 15) == 0)) &&
+        (a.yf == nullptr || ((a.cout & 3) == 0 && ((uintptr_t)a.yf & 15) == 0)) &&
+        (a.bias == nullptr || ((uintptr_t)a.bias & 15) == 0);
+    // this wave's 32 x kEpStride staging tile: in its tile's own (already
+    // consumed) partial-sum region, or its own slot
+    static_assert(KS == 1 || 32 * kEpStride <= WM * WN * 16 * 64, "staging tile fits a partial");
+    float *stage = KS > 1 ? s_part + (size_t)tile * (KS - 1) * (WM * WN * 16 * 64)
+                          : s_part + wave * (32 * kEpStride);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-            const int co = co0 + j * 32 + lr;
+            const int cs = co0 + j * 32;
+            if (vec_ok && (a.cout & 15) == 0 && cs < a.cout) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    stage[(8 * (r >> 2) + 4 * kh + (r & 3)) * kEpStride + lr] = acc[i][j][r];
+                wave_sync();
+                const int row = lane & 31, half = lane >> 5;
+                float v[16];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 t = *(const float4 *)(stage + row * kEpStride + half * 16 + 4 * q);
+                    v[4 * q] = t.x;
+                    v[4 * q + 1] = t.y;
+                    v[4 * q + 2] = t.z;
+                    v[4 * q + 3] = t.w;
+                }
+                wave_sync();
+                const int p = px0 + i * 32 + row;
+                const int co = cs + half * 16;
+                if (p >= npix || co >= a.cout) continue;
+                if (a.bias) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float4 t = ((const float4 *)(a.bias + co))[q];
+                        v[4 * q] += t.x;
+                        v[4 * q + 1] += t.y;
+                        v[4 * q + 2] += t.z;
+                        v[4 * q + 3] += t.w;
+                    }
+                }
+                if (a.relu) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) v[e] = fmaxf(v[e], 0.0f);
+                }
+                if (a.mask) {
+                    const uint4 *mp = (const uint4 *)(a.mask + (size_t)p * a.ldm + a.moff + co);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const uint4 m = mp[q];
+                        const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const uint16_t h = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
+                            if (!(bf16_to_f32(h) > 0.0f)) v[8 * q + e] = 0.0f;
+                        }
+                    }
+                }
+                if (a.yf) {
+                    float4 *fp = (float4 *)(a.yf + (size_t)p * a.cout + co);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        fp[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+                }
+                if (a.y) {
+                    uint4 *dp = (uint4 *)(a.y + (size_t)p * a.ldy + a.yoff + co);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        uint32_t ow[4];
+                        uint32_t iw[4] = {0u, 0u, 0u, 0u};
+                        if (a.accumulate) {
+                            const uint4 t = dp[q];
+                            iw[0] = t.x;
+                            iw[1] = t.y;
+                            iw[2] = t.z;
+                            iw[3] = t.w;
+                        }
+#pragma unroll
+                        for (int e2 = 0; e2 < 4; ++e2) {
+                            float lo = v[8 * q + 2 * e2], hi = v[8 * q + 2 * e2 + 1];
+                            if (a.accumulate) {
+                                lo += bf16_to_f32((uint16_t)(iw[e2] & 0xffffu));
+                                hi += bf16_to_f32((uint16_t)(iw[e2] >> 16));
+                            }
+                            ow[e2] = (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
+                        }
+                        dp[q] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                    }
+                }
+                continue;
+            }
+            const int co = cs + lr;
             if (co >= a.cout) continue;
             const float b = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
@@ -491,7 +605,8 @@ static hipError_t conv_launch(const ConvArgs &a, int tiles_co, hipStream_t s) {
     constexpr size_t R = WM * WN * 16 * 64 * sizeof(float);   // one partial tile
     if (tiles >= 2048 || K < 8) {
         const dim3 grid((tiles_px + 3) / 4, tiles_co);
-        hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 1>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 1>), grid, dim3(256),
+                           4 * 32 * kEpStride * sizeof(float), s, a);
     } else if (tiles >= 1024 || K < 16) {
         const dim3 grid((tiles_px + 1) / 2, tiles_co);
         hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 2>), grid, dim3(256), 2 * R, s, a);
@@ -535,9 +650,96 @@ hipError_t nn_flip(const uint16_t *w, uint16_t *wt, int cout, int cin, int cout_
     return hipGetLastError();
 }
 
+// Pooling and up-sampling on 8 channels (16 bytes) per thread: one coarse
+// pixel and its 2x2 fine pixels.  gather: the fine values are summed into
+// the coarse one (pooling forward, up-sampling backward); else the coarse
+// value is copied to the four fine ones (pooling backward, up-sampling
+// forward).  quarter: times 0.25 (pooling).  Same arithmetic, in the same
+// order, as pool2_kernel / up2_kernel.
+__global__ void resample8_kernel(const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
+                                 int yoff, int n, int hc, int wc, int c, int gather, int quarter,
+                                 int accumulate) {
+    const int groups = c >> 3;
+    const int total = n * hc * wc * groups;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int g = i % groups, q = i / groups;
+    const int xo = q % wc, r = q / wc;
+    const int yo = r % hc, nn = r / hc;
+    const int ch = g << 3;
+    const size_t coarse = (size_t)(nn * hc + yo) * wc + xo;
+    auto fine = [&](int t) -> size_t {
+        return (size_t)(nn * 2 * hc + 2 * yo + (t >> 1)) * (2 * wc) + 2 * xo + (t & 1);
+    };
+    auto unpack = [](uint4 u, float (&f)[8]) {
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] = bf16_to_f32((uint16_t)(w4[e >> 1] >> (16 * (e & 1))));
+    };
+    auto pack = [](const float (&f)[8]) {
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            w4[k] = (uint32_t)f32_to_bf16(f[2 * k]) | ((uint32_t)f32_to_bf16(f[2 * k + 1]) << 16);
+        return make_uint4(w4[0], w4[1], w4[2], w4[3]);
+    };
+    float v[8];
+    if (gather) {
+        float s8[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float f[8];
+            unpack(*(const uint4 *)(x + fine(t) * ldx + xoff + ch), f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s8[e] += f[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = quarter ? 0.25f * s8[e] : s8[e];
+        uint4 *dst = (uint4 *)(y + coarse * ldy + yoff + ch);
+        if (accumulate) {
+            float f[8];
+            unpack(*dst, f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] += f[e];
+        }
+        *dst = pack(v);
+    } else {
+        float f[8];
+        unpack(*(const uint4 *)(x + coarse * ldx + xoff + ch), f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = quarter ? 0.25f * f[e] : f[e];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint4 *dst = (uint4 *)(y + fine(t) * ldy + yoff + ch);
+            float o[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o[e] = v[e];
+            if (accumulate) {
+                unpack(*dst, f);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) o[e] += f[e];
+            }
+            *dst = pack(o);
+        }
+    }
+}
+
 hipError_t nn_resample(int op, const uint16_t *x, int ldx, int xoff, uint16_t *y, int ldy,
                        int yoff, int n, int h, int w, int c, int backward, int accumulate,
                        hipStream_t s) {
+    // 16-byte path: whole 8-channel groups, aligned rows, even sizes for pooling
+    const int hc = op == 0 ? h / 2 : h, wc = op == 0 ? w / 2 : w;
+    const bool vec = c % 8 == 0 && (ldx | xoff | ldy | yoff) % 8 == 0 &&
+                     ((uintptr_t)x & 15) == 0 && ((uintptr_t)y & 15) == 0 &&
+                     (op != 0 || (h % 2 == 0 && w % 2 == 0)) &&
+                     (int64_t)n * 4 * hc * wc * c < ((int64_t)1 << 31);
+    if (vec) {
+        const int64_t groups = (int64_t)n * hc * wc * (c / 8);
+        const int gather = op == 0 ? !backward : backward;
+        hipLaunchKernelGGL(resample8_kernel, dim3(blocks_for(groups)), dim3(256), 0, s, x, ldx,
+                           xoff, y, ldy, yoff, n, hc, wc, c, gather, op == 0 ? 1 : 0, accumulate);
+        return hipGetLastError();
+    }
     int64_t total;
     if (op == 0) total = backward ? (int64_t)n * h * w * c : (int64_t)n * (h / 2) * (w / 2) * c;
     else total = backward ? (int64_t)n * h * w * c : (int64_t)n * 4 * h * w * c;

@@ -76,6 +76,52 @@ def test_conv_forward(env, n, s, cin, cout, ldx, xoff, relu):
     assert np.all(from_bf16_bits(yb)[..., :16] == 0)     # outside the slice untouched
 
 
+# The epilogue finishes 16-channel groups with 16-byte accesses when the
+# channel count is a multiple of 16 and the output, mask and fp32 rows are
+# 16-byte aligned, else element by element: aligned and unaligned output
+# slices, half slabs (48 and 16 channels), 40 channels, and the one-, two-
+# and four-wave reductions (2 x 256^2, 2 x 10^2 and 12^2 pixels), with the
+# mask and accumulation options the network itself does not use.
+@pytest.mark.parametrize("n,s,cin,cout,ypad,relu", [
+    (1, 12, 32, 64, 16, 1), (1, 12, 32, 64, 3, 1), (2, 10, 16, 48, 8, 0), (1, 12, 16, 40, 8, 1),
+    (2, 64, 32, 16, 16, 1),
+    (2, 256, 16, 32, 16, 1), (2, 256, 16, 32, 5, 0)])
+def test_conv_mask_and_accumulate(env, n, s, cin, cout, ypad, relu):
+    torch, ctx = env
+    say("conv mask/accumulate", n, s, cin, cout, ypad, relu)
+    rng = np.random.default_rng(3 * cin + cout + ypad)
+    x = U.bf16_round(rng.normal(size=(n, s, s, cin)))
+    w = U.bf16_round(rng.normal(0, 0.2, size=(cout, 9, cin)))
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    ca = unet.cout_alloc(cout)
+    wpad = np.zeros((ca, 9, cin))
+    wpad[:cout] = w
+    ldy, ldm = cout + ypad, cout + 8
+    y0 = U.bf16_round(rng.normal(size=(n, s, s, ldy)))
+    m = U.bf16_round(rng.normal(size=(n, s, s, ldm)))
+    m[..., 8:][rng.random(size=(n, s, s, cout)) < 0.2] = 0.0     # exact zeros are masked too
+    dx = torch.from_numpy(to_bf16_bits(x)).cuda()
+    dw = torch.from_numpy(to_bf16_bits(wpad)).cuda()
+    db = torch.from_numpy(b.astype(np.float32)).cuda()
+    yb = torch.from_numpy(to_bf16_bits(y0)).cuda()
+    dm = torch.from_numpy(to_bf16_bits(m)).cuda()
+    yf = torch.zeros((n * s * s, cout), dtype=torch.float32, device="cuda")
+    mcx.mc_nn_conv3x3_async(ctx, dx, cin, 0, dw, db, yb, ldy, ypad, n, s, s, cin, cout,
+                            relu=relu, yf=yf, mask=dm, ldm=ldm, moff=8, accumulate=1)
+    torch.cuda.synchronize()
+    ref = U.conv3x3(x, w, b)
+    if relu:
+        ref = np.maximum(ref, 0)
+    ref = np.where(m[..., 8:8 + cout] > 0, ref, 0.0)
+    scale = np.abs(ref).max()
+    got = yf.cpu().numpy().astype(np.float64).reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-4 * scale
+    want = ref + y0[..., ypad:ypad + cout]
+    gb = from_bf16_bits(yb)
+    assert np.all(np.abs(gb[..., ypad:ypad + cout] - want) <= np.abs(want) * 2.0 ** -8 + 1e-4 * scale)
+    assert np.array_equal(gb[..., :ypad], y0[..., :ypad])     # outside the slice untouched
+
+
 @pytest.mark.parametrize("n,s,cin,cout,splits", [(1, 8, 16, 32, 1), (2, 16, 32, 64, 3),
                                                  (1, 16, 96, 32, 4), (4, 8, 128, 256, 2)])
 def test_conv_weight_and_input_gradients(env, n, s, cin, cout, splits):
@@ -130,6 +176,41 @@ def test_pool_upsample_and_mask(env):
     mcx.mc_nn_relu_mask_async(ctx, g, 48, 0, dx, 48, 0, 2 * 64, 48)
     torch.cuda.synchronize()
     assert np.array_equal(from_bf16_bits(g), (x > 0).astype(np.float64))
+
+
+# Pooling and up-sampling run 8 channels per thread when the channel count,
+# the slices and the sizes allow it, else element by element: both paths,
+# forward and backward, with accumulation into the output.
+@pytest.mark.parametrize("c,ldx,xoff,ldy,yoff,h,w", [
+    (16, 32, 16, 24, 8, 8, 8),        # 16-byte path
+    (12, 20, 4, 16, 2, 6, 10),        # element by element (12 channels, odd offsets)
+    (32, 32, 0, 40, 8, 6, 14)])       # 16-byte path, non-square
+def test_resample_paths(env, c, ldx, xoff, ldy, yoff, h, w):
+    torch, ctx = env
+    say("pool/up paths", c, ldx, xoff, ldy, yoff, h, w)
+    rng = np.random.default_rng(c + h + w)
+    n = 2
+    cases = [  # (op, backward, input (n, hi, wi), output (n, ho, wo), reference)
+        ("pool", 0, (h, w), (h // 2, w // 2), U.pool2),
+        ("pool", 1, (h // 2, w // 2), (h, w), U.pool2_grad),
+        ("up", 0, (h, w), (2 * h, 2 * w), U.up2),
+        ("up", 1, (2 * h, 2 * w), (h, w), U.up2_grad)]
+    for op, bw, (hi, wi), (ho, wo), ref_f in cases:
+        x = U.bf16_round(rng.normal(size=(n, hi, wi, ldx)))
+        y0 = U.bf16_round(rng.normal(size=(n, ho, wo, ldy)))
+        dx = torch.from_numpy(to_bf16_bits(x)).cuda()
+        dy = torch.from_numpy(to_bf16_bits(y0)).cuda()
+        fn = mcx.mc_nn_pool2_async if op == "pool" else mcx.mc_nn_upsample2_async
+        # sizes passed are the full-size image for pooling, the coarse one for up-sampling
+        hh, ww = (h, w)
+        fn(ctx, dx, ldx, xoff, dy, ldy, yoff, n, hh, ww, c, backward=bw, accumulate=1)
+        torch.cuda.synchronize()
+        want = ref_f(x[..., xoff:xoff + c]) + y0[..., yoff:yoff + c]
+        got = from_bf16_bits(dy)
+        assert np.all(np.abs(got[..., yoff:yoff + c] - want) <= np.abs(want) * 2.0 ** -8 + 1e-6), \
+            (op, bw)
+        assert np.array_equal(got[..., :yoff], y0[..., :yoff]), (op, bw)
+        assert np.array_equal(got[..., yoff + c:], y0[..., yoff + c:]), (op, bw)
 
 
 def small_net(torch, ctx, n=2, s=32, seed=3):
