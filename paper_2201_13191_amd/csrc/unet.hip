@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
 // 16-pixel slices of dY and of the shifted X are staged in LDS transposed
 // (channel-major) so each lane reads its 8 consecutive pixels in one 16-byte
 // LDS load.  Per-split partial tiles are reduced in a fixed order by
-// wgrad_reduce_kernel, so gradients are deterministic.
+// wgrad_group_kernel and wgrad_reduce_kernel, so gradients are deterministic.
 __global__ void __launch_bounds__(256) wgrad_kernel(const WgradArgs a) {
     __shared__ uint16_t s_dy[4][32][16 + 8];   // [wave][co][pixel] (+8 pad)
     __shared__ uint16_t s_x[4][32][16 + 8];    // [wave][ci][pixel]
@@ -376,12 +376,110 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const WgradArgs a) {
 }
 
 // dW[co][tap][ci] = sum over splits in order (fp32), optionally + bias grads
+// The same weight gradient for images whose width is a multiple of 16, with
+// all nine taps of a 32(co) x 32(ci) tile in one block: a wave takes 16-pixel
+// slices of one image row, stages the slice of dY and the three input rows
+// around it, 18 pixels wide (zeros outside the image), channel-major in its
+// own LDS, and issues the nine taps' products from there.  Split ranges are
+// whole slices; partial tiles are laid out as wgrad_kernel's.
+constexpr int kWgStride = 24;   // bf16 per staged channel row (16-byte aligned rows)
+
+__global__ void __launch_bounds__(256) wgrad9_kernel(const WgradArgs a) {
+    __shared__ __align__(16) uint16_t s_dy[4][32][kWgStride];      // [wave][co][pixel]
+    __shared__ __align__(16) uint16_t s_x[4][3][32][kWgStride];    // [wave][row][ci][pixel + 1]
+    __shared__ float s_acc[4][32][33];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32, split = blockIdx.z;
+    const int npix = a.n * a.h * a.w_;
+    const int per = (((npix + a.splits - 1) / a.splits) + 15) & ~15;
+    const int p_lo = min(npix, split * per), p_hi = min(npix, p_lo + per);
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+    const int kh = lane >> 5, lr = lane & 31;
+    auto put8 = [](uint16_t *dst, int stride, uint4 v) __attribute__((always_inline)) {
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[e * stride] = (uint16_t)(w4[e >> 1] >> (16 * (e & 1)));
+    };
+    for (int p0 = p_lo + wave * 16; p0 < p_hi; p0 += 64) {
+        const int row = p0 / a.w_;            // n * h + y of the slice's row
+        const int xx0 = p0 - row * a.w_;
+        const int yy = row % a.h;
+        {
+            // dY: pixel p0 + (lane & 15), channels co0 + 8 * (lane >> 4) .. +8
+            const int pl = lane & 15, c = co0 + (lane >> 4) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (c < a.cout) v = *(const uint4 *)(a.dy + (size_t)(p0 + pl) * a.ldy + a.yoff + c);
+            put8(&s_dy[wave][c - co0][pl], kWgStride, v);
+        }
+        // input rows yy - 1 .. yy + 1, pixels xx0 - 1 .. xx0 + 16, 8 channels per item
+        for (int t = lane; t < 3 * 18 * 4; t += 64) {
+            const int cq = t & 3, q = t >> 2;
+            const int r = q / 18, px = q - r * 18;
+            const int y2 = yy + r - 1, x2 = xx0 + px - 1, c = ci0 + cq * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y2 >= 0 && y2 < a.h && x2 >= 0 && x2 < a.w_ && c < a.cin)
+                v = *(const uint4 *)(a.x + ((size_t)(row + r - 1) * a.w_ + x2) * a.ldx + a.xoff + c);
+            put8(&s_x[wave][r][cq * 8][px], kWgStride, v);
+        }
+        wave_sync();
+        const bf16x8 av = *(const bf16x8 *)&s_dy[wave][lr][kh * 8];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                bf16x8 bv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = (short)s_x[wave][r][lr][kh * 8 + k + e];
+                acc[3 * r + k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[3 * r + k],
+                                                                         0, 0, 0);
+            }
+        wave_sync();      // the next slice overwrites the staging
+    }
+    // per tap: the 4 waves' tiles added in LDS in a fixed order, then this
+    // split's partial written
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s_acc[wave][8 * (r >> 2) + 4 * kh + (r & 3)][lr] = acc[t][r];
+        __syncthreads();
+        for (int i = threadIdx.x; i < 32 * 32; i += 256) {
+            const int rr = i >> 5, col = i & 31;
+            const float v = ((s_acc[0][rr][col] + s_acc[1][rr][col]) + s_acc[2][rr][col]) +
+                            s_acc[3][rr][col];
+            const int co = co0 + rr, ci = ci0 + col;
+            if (co < a.cout && ci < a.cin)
+                a.partial[(((size_t)split * 9 + t) * a.cout + co) * a.cin + ci] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Sum of the splits' partial tiles in a fixed order, in two levels: groups of
+// kWgGroup consecutive splits are summed in parallel (each into its group's
+// first slot), then the group sums in order.  partial is [split][tap][co][ci]
+// with n = 9*cout*cin elements per split.
+constexpr int kWgGroup = 32;
+
+__global__ void wgrad_group_kernel(float *partial, int splits, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k0 = blockIdx.y * kWgGroup, k1 = min(splits, k0 + kWgGroup);
+    float s = 0.0f;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) s += partial[(size_t)k * n + i];
+    partial[(size_t)k0 * n + i] = s;
+}
+
 __global__ void wgrad_reduce_kernel(const float *partial, int splits, int n, float *dw) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // partial is [split][tap][co][ci]; dw is [co][tap][ci] with n = 9*cout*cin
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * n + i];
+#pragma unroll 8
+    for (int k = 0; k < splits; k += kWgGroup) s += partial[(size_t)k * n + i];
     dw[i] = s;
 }
 
@@ -623,9 +721,18 @@ hipError_t nn_conv3x3(const ConvArgs &a, hipStream_t s) {
 }
 
 hipError_t nn_wgrad(const WgradArgs &a, float *tmp, float *dw, hipStream_t s) {
-    const dim3 grid((a.cout + 31) / 32, 9 * ((a.cin + 31) / 32), a.splits);
-    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, a);
+    if (a.w_ % 16 == 0 && (a.ldy | a.yoff) % 8 == 0 && ((uintptr_t)a.dy & 15) == 0) {
+        const dim3 grid((a.cout + 31) / 32, (a.cin + 31) / 32, a.splits);
+        hipLaunchKernelGGL(wgrad9_kernel, grid, dim3(256), 0, s, a);
+    } else {
+        const dim3 grid((a.cout + 31) / 32, 9 * ((a.cin + 31) / 32), a.splits);
+        hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, a);
+    }
     const int n = 9 * a.cout * a.cin;
+    if (a.splits > 1)
+        hipLaunchKernelGGL(wgrad_group_kernel,
+                           dim3(blocks_for(n), (a.splits + kWgGroup - 1) / kWgGroup), dim3(256),
+                           0, s, a.partial, a.splits, n);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
                        (const float *)a.partial, a.splits, n, tmp);
     hipLaunchKernelGGL(wgrad_permute_kernel, dim3(blocks_for(n)), dim3(256), 0, s,

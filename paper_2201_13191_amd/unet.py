@@ -34,8 +34,14 @@ LAYERS = [
     ("h_a", 32, 16, True), ("h_b", 16, 1, False),
 ]
 INTERNAL_COUT = {"h_b": 16}
-# pixel ranges of the bias-gradient sums (blocks per 64 channels)
+# (input channels, stored output channels) per layer
+LAYER_CH = {name: (ci, INTERNAL_COUT.get(name, co)) for name, ci, co, _ in LAYERS}
+# pixel ranges of the bias-gradient sums (blocks per 64 channels): at most
+# this many, and at least 256 pixels each
 BIAS_ROWS = 512
+# weight gradients: pixel splits chosen so that a layer's (32 x 32 tile,
+# split) blocks number about this many, with at least 256 pixels per split
+WGRAD_BLOCKS = 1024
 
 
 def cout_alloc(c):
@@ -113,7 +119,13 @@ class UNet:
     def _splits(self, name):
         s = self._in_size(name)
         npix = self.N * s * s
-        return int(max(1, min(64, npix // 1024)))
+        ci, coi = LAYER_CH[name]
+        tiles = -(-coi // 32) * -(-ci // 32)
+        return int(max(1, min(npix // 256, -(-WGRAD_BLOCKS // tiles))))
+
+    def _bias_rows(self, name):
+        s = self._in_size(name)
+        return int(max(1, min(BIAS_ROWS, self.N * s * s // 256)))
 
     def _in_size(self, name):
         lvl = {"e1a": 1, "e1b": 1, "e2a": 2, "e2b": 2, "e3a": 4, "e3b": 4, "b_a": 8, "b_b": 8,
@@ -222,7 +234,7 @@ class UNet:
                                       s, s, d["ci"], d["coi"], self._splits(name), self.ws,
                                       d["gw"], self.stream)
         mcx.mc_nn_bias_grad_async(self.ctx, gy, gy.shape[3], gyoff, n * s * s, d["coi"],
-                                  self.bias_ws, BIAS_ROWS, d["gb"], self.stream)
+                                  self.bias_ws, self._bias_rows(name), d["gb"], self.stream)
         if gx is not None:
             mcx.mc_nn_conv3x3_async(self.ctx, gy, gy.shape[3], gyoff, d["wt"], None, gx,
                                     gx.shape[3], gxoff, n, s, s, d["coi"], d["ci"], relu=0,

@@ -122,8 +122,13 @@ def test_conv_mask_and_accumulate(env, n, s, cin, cout, ypad, relu):
     assert np.array_equal(gb[..., :ypad], y0[..., :ypad])     # outside the slice untouched
 
 
+# Widths that are multiples of 16 take the nine-tap kernel (16-pixel row
+# slices), the others the per-tap one; split ranges that are not whole slices,
+# a 16-channel output and a partial input tile are included.
 @pytest.mark.parametrize("n,s,cin,cout,splits", [(1, 8, 16, 32, 1), (2, 16, 32, 64, 3),
-                                                 (1, 16, 96, 32, 4), (4, 8, 128, 256, 2)])
+                                                 (1, 16, 96, 32, 4), (4, 8, 128, 256, 2),
+                                                 (2, 32, 48, 16, 5), (1, 64, 16, 64, 7),
+                                                 (3, 48, 64, 96, 1), (2, 32, 16, 32, 70)])
 def test_conv_weight_and_input_gradients(env, n, s, cin, cout, splits):
     torch, ctx = env
     say("wgrad", n, s, cin, cout, splits)
