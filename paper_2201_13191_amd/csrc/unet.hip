@@ -54,6 +54,127 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Epilogue of a wave's 32*WM x 32*WN output tile (pixels px0.., channels
+// co0..): bias, ReLU, mask, fp32 and bf16 stores, accumulation.  Element r of
+// a 32x32 accumulator is row 8*(r/4) + 4*(lane/32) + r%4, column lane%32.
+// When the channel count is a multiple of 16 and the rows are 16-byte
+// aligned, a slab of 32 channels is turned around in `stage` (32 x kEpStride
+// floats of LDS owned by the wave; row = pixel), so that each lane finishes
+// 16 consecutive channels of one pixel with 16-byte loads and stores;
+// otherwise element by element.
+template <int WM, int WN>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs &a, f32x16 (&acc)[WM][WN], int px0,
+                                              int co0, int npix, float *stage, int lane) {
+    const int kh = lane >> 5, lr = lane & 31;
+    const bool vec_ok =
+        (a.y == nullptr || (((a.ldy | a.yoff) & 7) == 0 && ((uintptr_t)a.y & 15) == 0)) &&
+        (a.mask == nullptr || (((a.ldm | a.moff) & 7) == 0 && ((uintptr_t)a.mask & 15) == 0)) &&
+        (a.yf == nullptr || ((a.cout & 3) == 0 && ((uintptr_t)a.yf & 15) == 0)) &&
+        (a.bias == nullptr || ((uintptr_t)a.bias & 15) == 0);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const int cs = co0 + j * 32;
+            if (vec_ok && (a.cout & 15) == 0 && cs < a.cout) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    stage[(8 * (r >> 2) + 4 * kh + (r & 3)) * kEpStride + lr] = acc[i][j][r];
+                wave_sync();
+                const int row = lane & 31, half = lane >> 5;
+                float v[16];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 t = *(const float4 *)(stage + row * kEpStride + half * 16 + 4 * q);
+                    v[4 * q] = t.x;
+                    v[4 * q + 1] = t.y;
+                    v[4 * q + 2] = t.z;
+                    v[4 * q + 3] = t.w;
+                }
+                wave_sync();
+                const int p = px0 + i * 32 + row;
+                const int co = cs + half * 16;
+                if (p >= npix || co >= a.cout) continue;
+                if (a.bias) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float4 t = ((const float4 *)(a.bias + co))[q];
+                        v[4 * q] += t.x;
+                        v[4 * q + 1] += t.y;
+                        v[4 * q + 2] += t.z;
+                        v[4 * q + 3] += t.w;
+                    }
+                }
+                if (a.relu) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) v[e] = fmaxf(v[e], 0.0f);
+                }
+                if (a.mask) {
+                    const uint4 *mp = (const uint4 *)(a.mask + (size_t)p * a.ldm + a.moff + co);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const uint4 m = mp[q];
+                        const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const uint16_t h = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
+                            if (!(bf16_to_f32(h) > 0.0f)) v[8 * q + e] = 0.0f;
+                        }
+                    }
+                }
+                if (a.yf) {
+                    float4 *fp = (float4 *)(a.yf + (size_t)p * a.cout + co);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        fp[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+                }
+                if (a.y) {
+                    uint4 *dp = (uint4 *)(a.y + (size_t)p * a.ldy + a.yoff + co);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        uint32_t ow[4];
+                        uint32_t iw[4] = {0u, 0u, 0u, 0u};
+                        if (a.accumulate) {
+                            const uint4 t = dp[q];
+                            iw[0] = t.x;
+                            iw[1] = t.y;
+                            iw[2] = t.z;
+                            iw[3] = t.w;
+                        }
+#pragma unroll
+                        for (int e2 = 0; e2 < 4; ++e2) {
+                            float lo = v[8 * q + 2 * e2], hi = v[8 * q + 2 * e2 + 1];
+                            if (a.accumulate) {
+                                lo += bf16_to_f32((uint16_t)(iw[e2] & 0xffffu));
+                                hi += bf16_to_f32((uint16_t)(iw[e2] >> 16));
+                            }
+                            ow[e2] = (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
+                        }
+                        dp[q] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                    }
+                }
+                continue;
+            }
+            const int co = cs + lr;
+            if (co >= a.cout) continue;
+            const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int p = px0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (p >= npix) continue;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.mask && !(bf16_to_f32(a.mask[(size_t)p * a.ldm + a.moff + co]) > 0.0f)) v = 0.0f;
+                if (a.yf) a.yf[(size_t)p * a.cout + co] = v;
+                if (a.y) {
+                    uint16_t *dst = a.y + (size_t)p * a.ldy + a.yoff + co;
+                    if (a.accumulate) v += bf16_to_f32(*dst);
+                    *dst = f32_to_bf16(v);
+                }
+            }
+        }
+}
+
 template <int WM, int WN, int KS>
 __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
     // 4 waves: 4 / KS output tiles of 32*WM pixels x 32*WN channels, each
@@ -173,123 +294,136 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(const ConvArgs a) {
         }
     }
     if (!live) return;
-    // epilogue: element r of a 32x32 accumulator is row 8*(r/4) + 4*(lane/32) + r%4,
-    // column lane%32.  When the channel count is a multiple of 16 and the
-    // rows are 16-byte aligned, a slab of 32 channels is turned around in LDS
-    // (row = pixel), so that each lane finishes 16 consecutive channels of
-    // one pixel with 16-byte loads and stores; otherwise element by element.
-    const bool vec_ok =
-        (a.y == nullptr || (((a.ldy | a.yoff) & 7) == 0 && ((uintptr_t)a.y & 15) == 0)) &&
-        (a.mask == nullptr || (((a.ldm | a.moff) & 7) == 0 && ((uintptr_t)a.mask & 15) == 0)) &&
-        (a.yf == nullptr || ((a.cout & 3) == 0 && ((uintptr_t)a.yf & 15) == 0)) &&
-        (a.bias == nullptr || ((uintptr_t)a.bias & 15) == 0);
     // this wave's 32 x kEpStride staging tile: in its tile's own (already
     // consumed) partial-sum region, or its own slot
     static_assert(KS == 1 || 32 * kEpStride <= WM * WN * 16 * 64, "staging tile fits a partial");
     float *stage = KS > 1 ? s_part + (size_t)tile * (KS - 1) * (WM * WN * 16 * 64)
                           : s_part + wave * (32 * kEpStride);
+    conv_epilogue<WM, WN>(a, acc, px0, co0, npix, stage, lane);
+}
+
+// The same convolution for images whose width is a multiple of 64, on layers
+// with enough tiles for one wave each (2 x 32 pixels x 32*WN channels): a
+// wave's 64 output pixels lie in one image row.  The reduction runs over
+// 16-channel chunks; for each chunk every wave stages the three input rows
+// around its pixels (66 pixels wide, zeros outside the image) and the block
+// stages the nine taps' weights, pixel- and channel-major as in memory, in
+// LDS, so each input value is loaded once per chunk instead of once per tap.
+// The next chunk's loads are in flight in registers while the products of
+// the current one are issued.
+constexpr int kLdsInPx = 66;                          // staged pixels per row
+constexpr int kLdsInElems = 3 * kLdsInPx * 16;        // one wave's rows, one chunk (bf16)
+
+template <int WN>
+constexpr int lds_w_elems() { return 9 * 32 * WN * 16; }   // the block's weights, one chunk
+
+template <int WN>
+constexpr size_t conv_lds_bytes() { return (4 * kLdsInElems + lds_w_elems<WN>()) * 2; }
+
+#ifndef MCX_CONV_LDS
+#define MCX_CONV_LDS 1
+#endif
+constexpr bool conv_lds_enabled = MCX_CONV_LDS != 0;
+
+template <int WN>
+__global__ void __launch_bounds__(256) conv3x3_lds_kernel(const ConvArgs a) {
+    constexpr int WM = 2;
+    constexpr int kInItems = 3 * kLdsInPx * 2;                  // 16-byte items per wave
+    constexpr int kInPer = (kInItems + 63) / 64;
+    constexpr int kWItems = 9 * 32 * WN * 2;                    // 16-byte items per block
+    constexpr int kWPer = (kWItems + 255) / 256;
+    static_assert(32 * kEpStride * 4 <= kLdsInElems * 2, "epilogue staging fits a wave's rows");
+    extern __shared__ __align__(16) float s_dyn[];
+    uint16_t *lds = (uint16_t *)s_dyn;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kh = lane >> 5, lr = lane & 31;
+    const int npix = a.n * a.h * a.w_;
+    const int px0 = (blockIdx.x * 4 + wave) * (32 * WM);
+    const int co0 = blockIdx.y * (32 * WN);
+    const bool live = px0 < npix;       // no early return: the block meets at barriers
+    const int row = live ? px0 / a.w_ : 0;   // n * h + y of the wave's pixels
+    const int x0 = px0 - row * a.w_;
+    const int yy = row % a.h;
+    const int kc = a.cin >> 4;
+    const size_t wk = (size_t)9 * a.cin;
+    uint4 rin[kInPer], rw[kWPer];
+    auto load_chunk = [&](int c) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < kInPer; ++m) {
+            const int t = lane + 64 * m;
+            const int q = t >> 1, r = q / kLdsInPx, px = q - r * kLdsInPx;
+            const int y2 = yy + r - 1, x2 = x0 + px - 1;
+            rin[m] = make_uint4(0u, 0u, 0u, 0u);
+            if (live && t < kInItems && y2 >= 0 && y2 < a.h && x2 >= 0 && x2 < a.w_)
+                rin[m] = *(const uint4 *)(a.x + ((size_t)(row + r - 1) * a.w_ + x2) * a.ldx +
+                                          a.xoff + c * 16 + (t & 1) * 8);
+        }
+#pragma unroll
+        for (int m = 0; m < kWPer; ++m) {
+            const int u = threadIdx.x + 256 * m;
+            const int rest = u >> 1, col = rest % (32 * WN), tap = rest / (32 * WN);
+            rw[m] = make_uint4(0u, 0u, 0u, 0u);
+            if (u < kWItems)
+                rw[m] = *(const uint4 *)(a.w + (size_t)(co0 + col) * wk + (size_t)tap * a.cin +
+                                         c * 16 + (u & 1) * 8);
+        }
+    };
+    auto store_chunk = [&]() __attribute__((always_inline)) {
+        uint16_t *in = lds + wave * kLdsInElems;
+#pragma unroll
+        for (int m = 0; m < kInPer; ++m) {
+            const int t = lane + 64 * m;
+            if (t < kInItems) *(uint4 *)(in + (t >> 1) * 16 + (t & 1) * 8) = rin[m];
+        }
+        uint16_t *wl = lds + 4 * kLdsInElems;
+#pragma unroll
+        for (int m = 0; m < kWPer; ++m) {
+            const int u = threadIdx.x + 256 * m;
+            if (u < kWItems) *(uint4 *)(wl + (u >> 1) * 16 + (u & 1) * 8) = rw[m];
+        }
+    };
+    f32x16 acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const int cs = co0 + j * 32;
-            if (vec_ok && (a.cout & 15) == 0 && cs < a.cout) {
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    stage[(8 * (r >> 2) + 4 * kh + (r & 3)) * kEpStride + lr] = acc[i][j][r];
-                wave_sync();
-                const int row = lane & 31, half = lane >> 5;
-                float v[16];
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    load_chunk(0);
+    store_chunk();
+    __syncthreads();
+    for (int c = 0; c < kc; ++c) {
+        if (c + 1 < kc) load_chunk(c + 1);
+        const uint16_t *in = lds + wave * kLdsInElems;
+        const uint16_t *wl = lds + 4 * kLdsInElems;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 t = *(const float4 *)(stage + row * kEpStride + half * 16 + 4 * q);
-                    v[4 * q] = t.x;
-                    v[4 * q + 1] = t.y;
-                    v[4 * q + 2] = t.z;
-                    v[4 * q + 3] = t.w;
-                }
-                wave_sync();
-                const int p = px0 + i * 32 + row;
-                const int co = cs + half * 16;
-                if (p >= npix || co >= a.cout) continue;
-                if (a.bias) {
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float4 t = ((const float4 *)(a.bias + co))[q];
-                        v[4 * q] += t.x;
-                        v[4 * q + 1] += t.y;
-                        v[4 * q + 2] += t.z;
-                        v[4 * q + 3] += t.w;
-                    }
-                }
-                if (a.relu) {
+            for (int k = 0; k < 3; ++k) {
+                bf16x8 av[WM], bv[WN];
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) v[e] = fmaxf(v[e], 0.0f);
-                }
-                if (a.mask) {
-                    const uint4 *mp = (const uint4 *)(a.mask + (size_t)p * a.ldm + a.moff + co);
+                for (int i = 0; i < WM; ++i)
+                    av[i] = *(const bf16x8 *)(in + (r * kLdsInPx + i * 32 + lr + k) * 16 + kh * 8);
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const uint4 m = mp[q];
-                        const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+                for (int j = 0; j < WN; ++j)
+                    bv[j] = *(const bf16x8 *)(wl + ((3 * r + k) * 32 * WN + j * 32 + lr) * 16 +
+                                              kh * 8);
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const uint16_t h = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
-                            if (!(bf16_to_f32(h) > 0.0f)) v[8 * q + e] = 0.0f;
-                        }
-                    }
-                }
-                if (a.yf) {
-                    float4 *fp = (float4 *)(a.yf + (size_t)p * a.cout + co);
+                for (int i = 0; i < WM; ++i)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        fp[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-                }
-                if (a.y) {
-                    uint4 *dp = (uint4 *)(a.y + (size_t)p * a.ldy + a.yoff + co);
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        uint32_t ow[4];
-                        uint32_t iw[4] = {0u, 0u, 0u, 0u};
-                        if (a.accumulate) {
-                            const uint4 t = dp[q];
-                            iw[0] = t.x;
-                            iw[1] = t.y;
-                            iw[2] = t.z;
-                            iw[3] = t.w;
-                        }
-#pragma unroll
-                        for (int e2 = 0; e2 < 4; ++e2) {
-                            float lo = v[8 * q + 2 * e2], hi = v[8 * q + 2 * e2 + 1];
-                            if (a.accumulate) {
-                                lo += bf16_to_f32((uint16_t)(iw[e2] & 0xffffu));
-                                hi += bf16_to_f32((uint16_t)(iw[e2] >> 16));
-                            }
-                            ow[e2] = (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
-                        }
-                        dp[q] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                    }
-                }
-                continue;
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j],
+                                                                             acc[i][j], 0, 0, 0);
             }
-            const int co = cs + lr;
-            if (co >= a.cout) continue;
-            const float b = a.bias ? a.bias[co] : 0.0f;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int p = px0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (p >= npix) continue;
-                float v = acc[i][j][r] + b;
-                if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.mask && !(bf16_to_f32(a.mask[(size_t)p * a.ldm + a.moff + co]) > 0.0f)) v = 0.0f;
-                if (a.yf) a.yf[(size_t)p * a.cout + co] = v;
-                if (a.y) {
-                    uint16_t *dst = a.y + (size_t)p * a.ldy + a.yoff + co;
-                    if (a.accumulate) v += bf16_to_f32(*dst);
-                    *dst = f32_to_bf16(v);
-                }
-            }
+        __syncthreads();       // every wave is done with this chunk
+        if (c + 1 < kc) {
+            store_chunk();
+            __syncthreads();
         }
+    }
+    if (!live) return;
+    // the epilogue stages in this wave's rows (no longer read)
+    conv_epilogue<WM, WN>(a, acc, px0, co0, npix, (float *)(lds + wave * kLdsInElems), lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,7 +835,10 @@ static hipError_t conv_launch(const ConvArgs &a, int tiles_co, hipStream_t s) {
     const long tiles = (long)tiles_px * tiles_co;
     const int K = 9 * (a.cin / 16);
     constexpr size_t R = WM * WN * 16 * 64 * sizeof(float);   // one partial tile
-    if (tiles >= 2048 || K < 8) {
+    if (WM == 2 && tiles >= 2048 && a.w_ % 64 == 0 && conv_lds_enabled) {
+        const dim3 grid((tiles_px + 3) / 4, tiles_co);
+        hipLaunchKernelGGL((conv3x3_lds_kernel<WN>), grid, dim3(256), conv_lds_bytes<WN>(), s, a);
+    } else if (tiles >= 2048 || K < 8) {
         const dim3 grid((tiles_px + 3) / 4, tiles_co);
         hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 1>), grid, dim3(256),
                            4 * 32 * kEpStride * sizeof(float), s, a);
