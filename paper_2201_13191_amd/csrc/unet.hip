@@ -426,6 +426,135 @@ __global__ void __launch_bounds__(256) conv3x3_lds_kernel(const ConvArgs a) {
     conv_epilogue<WM, WN>(a, acc, px0, co0, npix, (float *)(lds + wave * kLdsInElems), lane);
 }
 
+// The same staging for layers with few tiles, whose reduction is split over
+// KS waves of a block (16-channel chunks c = ks, ks + KS, ...; partial tiles
+// added in LDS in a fixed order).  Each wave stages its chunk's input window
+// in its own LDS rows, with the weights read through L1/L2.  The window is
+// the tile's image rows and one more on each side: for widths that are
+// multiples of 64 one row of 66 pixels, for widths of 16 or 32 (a 64-pixel
+// tile is 4 or 2 whole rows) the rows at their full width plus the zero
+// columns at both ends.
+template <int WN, int KS>
+__global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a) {
+    constexpr int WM = 2, TPB = 4 / KS;
+    constexpr int R = WM * WN * 16;                   // floats per lane of a partial tile
+    constexpr int kInPer = (3 * kLdsInPx * 2 + 63) / 64;
+    static_assert(32 * kEpStride <= R * 64, "epilogue staging fits a partial tile");
+    extern __shared__ __align__(16) float s_dyn[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = wave / KS, ks = wave - tile * KS;
+    const int kh = lane >> 5, lr = lane & 31;
+    uint16_t *in = (uint16_t *)s_dyn + wave * kLdsInElems;
+    const int npix = a.n * a.h * a.w_;
+    const int px0 = (blockIdx.x * TPB + tile) * (32 * WM);
+    const int co0 = blockIdx.y * (32 * WN);
+    const bool live = px0 < npix;       // no early return: the block meets at barriers
+    const bool wide = a.w_ >= 64;
+    const int nr = wide ? 1 : 64 / a.w_;              // image rows of the tile
+    const int wn = wide ? kLdsInPx : a.w_ + 2;        // staged pixels per row
+    const int row0 = live ? px0 / a.w_ : 0;           // n * h + y of the tile's first row
+    const int xs = px0 - row0 * a.w_;                 // its first column (0 for whole rows)
+    const int yy0 = row0 % a.h;
+    const int items = (nr + 2) * wn * 2;              // 16-byte items of the window
+    // staged pixel of this lane's rows for tap (0, 0)
+    int aoff[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        const int j = i * 32 + lr;
+        const int ry = wide ? 0 : j / a.w_;
+        aoff[i] = ry * wn + (j - ry * (wide ? 0 : a.w_));
+    }
+    const int kc = a.cin >> 4;
+    const size_t wk = (size_t)9 * a.cin;
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    uint4 rin[kInPer];
+    auto load_chunk = [&](int c) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < kInPer; ++m) {
+            const int t = lane + 64 * m;
+            const int q = t >> 1, r = q / wn, px = q - r * wn;
+            const int y2 = yy0 + r - 1, x2 = xs + px - 1;
+            rin[m] = make_uint4(0u, 0u, 0u, 0u);
+            if (t < items && y2 >= 0 && y2 < a.h && x2 >= 0 && x2 < a.w_)
+                rin[m] = *(const uint4 *)(a.x + ((size_t)(row0 + r - 1) * a.w_ + x2) * a.ldx +
+                                          a.xoff + c * 16 + (t & 1) * 8);
+        }
+    };
+    if (live && ks < kc) {
+        load_chunk(ks);
+        for (int c = ks; c < kc; c += KS) {
+#pragma unroll
+            for (int m = 0; m < kInPer; ++m) {
+                const int t = lane + 64 * m;
+                if (t < items) *(uint4 *)(in + (t >> 1) * 16 + (t & 1) * 8) = rin[m];
+            }
+            wave_sync();
+            if (c + KS < kc) load_chunk(c + KS);   // in flight during the products
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int tap = 3 * r + k;
+                    bf16x8 av[WM], bv[WN];
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+                        av[i] = *(const bf16x8 *)(in + (aoff[i] + r * wn + k) * 16 + kh * 8);
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+                        bv[j] = *(const bf16x8 *)(a.w + (size_t)(co0 + j * 32 + lr) * wk +
+                                                  (size_t)tap * a.cin + c * 16 + kh * 8);
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                av[i], bv[j], acc[i][j], 0, 0, 0);
+                }
+            wave_sync();      // the next chunk overwrites the rows
+        }
+    }
+    // partial tiles of waves ks = 1 .. KS-1 over the (no longer read) rows,
+    // [tile][ks-1][register][lane]
+    __syncthreads();
+    float *mine = s_dyn + ((size_t)(tile * (KS - 1) + (ks > 0 ? ks - 1 : 0)) * R) * 64;
+    if (ks > 0) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) mine[((i * WN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+    }
+    __syncthreads();
+    if (ks > 0) return;
+    const float *base = s_dyn + (size_t)tile * (KS - 1) * R * 64;
+#pragma unroll 1
+    for (int q = 0; q < KS - 1; ++q) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc[i][j][r] += base[((size_t)q * R + (i * WN + j) * 16 + r) * 64 + lane];
+    }
+    if (!live) return;
+    conv_epilogue<WM, WN>(a, acc, px0, co0, npix, (float *)base, lane);
+}
+
+template <int WN, int KS>
+constexpr size_t conv_lds_split_bytes() {
+    constexpr size_t rows = 4 * kLdsInElems * 2;
+    constexpr size_t parts = (size_t)(4 / KS) * (KS - 1) * 2 * WN * 16 * 64 * sizeof(float);
+    return rows > parts ? rows : parts;
+}
+
 // ---------------------------------------------------------------------------
 // weight gradient: dW[co][tap][ci] = sum over pixels of dY[p][co] * X[p + tap][ci].
 // One block = 4 waves = a 32(co) x 32(ci) tile of one tap over a pixel range;
@@ -842,6 +971,18 @@ static hipError_t conv_launch(const ConvArgs &a, int tiles_co, hipStream_t s) {
         const dim3 grid((tiles_px + 3) / 4, tiles_co);
         hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 1>), grid, dim3(256),
                            4 * 32 * kEpStride * sizeof(float), s, a);
+    } else if (WM == 2 && conv_lds_enabled &&
+               (a.w_ % 64 == 0 || (a.w_ >= 16 && 64 % a.w_ == 0 && a.h % (64 / a.w_) == 0))) {
+        // the reduction split over 2 or 4 waves by 16-channel chunks
+        if (tiles >= 1024 || a.cin < 64) {
+            const dim3 grid((tiles_px + 1) / 2, tiles_co);
+            hipLaunchKernelGGL((conv3x3_lds_split_kernel<WN, 2>), grid, dim3(256),
+                               (conv_lds_split_bytes<WN, 2>()), s, a);
+        } else {
+            const dim3 grid(tiles_px, tiles_co);
+            hipLaunchKernelGGL((conv3x3_lds_split_kernel<WN, 4>), grid, dim3(256),
+                               (conv_lds_split_bytes<WN, 4>()), s, a);
+        }
     } else if (tiles >= 1024 || K < 16) {
         const dim3 grid((tiles_px + 1) / 2, tiles_co);
         hipLaunchKernelGGL((conv3x3_kernel<WM, WN, 2>), grid, dim3(256), 2 * R, s, a);

@@ -41,16 +41,18 @@ def rel(a, b):
 
 
 # The kernel splits each tile's reduction over 1, 2 or 4 waves by the layer's
-# tile count: (2, 256, ...) takes the one-wave path, which on images whose
-# width is a multiple of 64 stages the input rows and weights in LDS (with 32
-# and 64 output channels, and three 16-channel chunks), (1, 256, ...) the
-# two-wave one, the others the four-wave one (or two waves when the
-# reduction is short).
+# tile count: (2, 256, ...) takes the one-wave path, (1, 256, ...) and
+# (2, 16, 32, ...) the two-wave one, the others the four-wave one (or two
+# waves when the reduction is short).  Images whose width is a multiple of 64,
+# or 16 or 32 wide, stage their input rows in LDS per 16-channel chunk (wide
+# windows of 66 pixels, or 2 and 4 whole rows); the 8-, 9-, 12- and 5-pixel
+# images read their operands directly.
 @pytest.mark.parametrize("n,s,cin,cout,ldx,xoff,relu", [
     (1, 8, 16, 32, 16, 0, 1), (2, 16, 32, 64, 48, 16, 1), (1, 12, 48, 128, 48, 0, 0),
     (3, 9, 16, 16, 32, 16, 1), (1, 32, 384, 128, 384, 0, 1), (2, 5, 64, 1, 64, 0, 0),
     (2, 256, 16, 32, 32, 16, 1), (1, 256, 32, 32, 32, 0, 1),
-    (2, 256, 32, 64, 32, 0, 1), (2, 256, 48, 32, 64, 16, 0)])
+    (2, 256, 32, 64, 32, 0, 1), (2, 256, 48, 32, 64, 16, 0),
+    (1, 64, 64, 64, 64, 0, 1), (2, 16, 128, 64, 128, 0, 1)])
 def test_conv_forward(env, n, s, cin, cout, ldx, xoff, relu):
     torch, ctx = env
     say("conv", n, s, cin, cout, ldx, xoff, relu)
