@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--pd-point-only", dest="pd_mixed", action="store_false",
                     help="the point detector also for Rayleigh events (default: mixed, Rayleigh "
                          "pseudo-particles along their own law)")
+    ap.add_argument("--pd-launch", default="", metavar="BLOCK,BPC,EVENT_BATCH",
+                    help="launch shape for the point-detector runs (default: the analog one)")
     ap.add_argument("--pd-fraction", type=float, default=0.1,
                     help="point-detector photons as a fraction of the step's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -304,6 +306,10 @@ def main():
             f"{tuning['event_batch']}, table layout {tuning['table_layout']}, "
             f"{tuning['candidates']} candidates, {tuning['rejected']} rejected")
 
+    launch_shape = ((blk, bpc, eb) if args.launch else
+                    (tuning["block"], tuning["blocks_per_cu"], tuning["event_batch"]) if tuning
+                    else (0, 0, 0))
+
     # exact algorithmic work of one step (untimed counting pass)
     log("counting pass")
     g.stats(True)
@@ -369,6 +375,8 @@ def main():
         n_pd = max(1, int(n * args.pd_fraction))
         g.set_estimator(mcx.MC_SCORE_POINT_MIXED if args.pd_mixed else mcx.MC_SCORE_POINT,
                         args.pd_split, args.pd_rr)
+        if args.pd_launch:
+            g.set_launch(*[int(v) for v in args.pd_launch.split(",")])
         mcx.mc_project_async(g.ctx, w["angle"], n_pd, w["seed"], prim, scat, stream)
         torch.cuda.synchronize()
         imgs, times = [], []
@@ -381,6 +389,8 @@ def main():
             times.append(a.elapsed_time(b) * 1e-3)
             imgs.append(scat.cpu().numpy())
         g.set_estimator(mcx.MC_SCORE_ANALOG)
+        if args.pd_launch:
+            g.set_launch(*launch_shape)
         t_pd = float(np.mean(times))
         r_pd = metrics.pair_rel_rms(*imgs)
         n2_pd = n_pd * (r_pd / 0.02) ** 2
