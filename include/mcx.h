@@ -551,8 +551,9 @@ typedef struct mc_conv3x3 {
  * it computes a convolution's input gradient through the previous ReLU. */
 mc_status mc_nn_conv3x3_async(mc_ctx *ctx, const mc_conv3x3 *args, void *stream);
 /* dw[co][tap][ci] (fp32) = sum over pixels of dy[p][co] * x[p + tap][ci];
- * deterministic (per-split partials summed in order).  workspace: at least
- * (splits + 1) * 9 * cout * cin floats; cin, cout multiples of 16. */
+ * deterministic (per-split partials summed in a fixed order).  workspace: at
+ * least (splits + 1) * 9 * cout * cin floats; cin, cout multiples of 16;
+ * splits 1..4096; n * h * w under 2^30 (else MC_E_INVALID_ARG). */
 mc_status mc_nn_conv3x3_wgrad_async(mc_ctx *ctx, const uint16_t *x, int ldx, int xoff,
                                     const uint16_t *dy, int ldy, int yoff, int n, int h, int w,
                                     int cin, int cout, int splits, float *workspace, float *dw,

@@ -1697,8 +1697,10 @@ mc_status mc_nn_conv3x3_wgrad_async(mc_ctx *c, const uint16_t *x, int ldx, int x
                                     void *stream) {
     if (!c) return MC_E_INVALID_ARG;
     if (!x || !dy || !ws || !dw || n < 1 || h < 1 || w < 1 || cin < 16 || cin % 16 ||
-        cout < 16 || cout % 16 || splits < 1 || splits > 4096)
-        return fail(c, MC_E_INVALID_ARG, "wgrad: bad arguments (cin, cout multiples of 16)");
+        cout < 16 || cout % 16 || splits < 1 || splits > 4096 ||
+        (int64_t)n * h * w >= ((int64_t)1 << 30))
+        return fail(c, MC_E_INVALID_ARG,
+                    "wgrad: bad arguments (cin, cout multiples of 16; under 2^30 pixels)");
     if (ldx % 16 || xoff % 16 || xoff + cin > ldx || yoff + cout > ldy || !aligned16(x))
         return fail(c, MC_E_INVALID_ARG, "wgrad: bad slices");
     WgradArgs k;
