@@ -930,6 +930,27 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16
 }
 
 // g[p][c] = 0 where y[p][c] <= 0: gradient through a ReLU whose output is y
+// 8 channels (16 bytes) per thread
+__global__ void relu_mask8_kernel(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy,
+                                  int yoff, int npix, int c) {
+    const int groups = c >> 3;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * groups) return;
+    const int p = i / groups, ch = (i - p * groups) << 3;
+    const uint4 yv = *(const uint4 *)(y + (size_t)p * ldy + yoff + ch);
+    uint4 *gp = (uint4 *)(g + (size_t)p * ldg + goff + ch);
+    const uint4 gv = *gp;
+    const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+    uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t lo = bf16_to_f32((uint16_t)(yw[k] & 0xffffu)) > 0.0f ? 0x0000ffffu : 0u;
+        const uint32_t hi = bf16_to_f32((uint16_t)(yw[k] >> 16)) > 0.0f ? 0xffff0000u : 0u;
+        gw[k] &= lo | hi;
+    }
+    *gp = make_uint4(gw[0], gw[1], gw[2], gw[3]);
+}
+
 __global__ void relu_mask_kernel(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy,
                                  int yoff, int64_t npix, int c) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1153,6 +1174,12 @@ hipError_t nn_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, i
 
 hipError_t nn_relu_mask(uint16_t *g, int ldg, int goff, const uint16_t *y, int ldy, int yoff,
                         int64_t npix, int c, hipStream_t s) {
+    if (c % 8 == 0 && (ldg | goff | ldy | yoff) % 8 == 0 && ((uintptr_t)g & 15) == 0 &&
+        ((uintptr_t)y & 15) == 0 && npix * c < ((int64_t)1 << 31)) {
+        hipLaunchKernelGGL(relu_mask8_kernel, dim3(blocks_for(npix * (c / 8))), dim3(256), 0, s, g,
+                           ldg, goff, y, ldy, yoff, (int)npix, c);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c)), dim3(256), 0, s, g, ldg, goff,
                        y, ldy, yoff, npix, c);
     return hipGetLastError();

@@ -225,9 +225,12 @@ class UNet:
         torch.cuda.synchronize()
         return float(self.loss_partial.cpu().double().sum().item() / self.out32.shape[0])
 
-    def _layer_back(self, name, x, xoff, gy, gyoff, gx=None, gxoff=0):
+    def _layer_back(self, name, x, xoff, gy, gyoff, gx=None, gxoff=0, relu_of=None):
         """Gradients of layer `name`: dW, db from its input x (slice) and the
-        (already masked) output gradient gy (slice); input gradient into gx."""
+        (already masked) output gradient gy (slice); input gradient into gx,
+        zeroed where relu_of (the activation gx belongs to, same slice) is not
+        positive when given (the previous ReLU's derivative, applied in the
+        convolution's epilogue)."""
         d = self.L[name]
         n, s = x.shape[0], x.shape[1]
         mcx.mc_nn_conv3x3_wgrad_async(self.ctx, x, x.shape[3], xoff, gy, gy.shape[3], gyoff, n,
@@ -236,9 +239,11 @@ class UNet:
         mcx.mc_nn_bias_grad_async(self.ctx, gy, gy.shape[3], gyoff, n * s * s, d["coi"],
                                   self.bias_ws, self._bias_rows(name), d["gb"], self.stream)
         if gx is not None:
+            mask = dict(mask=relu_of, ldm=relu_of.shape[3], moff=gxoff) if relu_of is not None \
+                else {}
             mcx.mc_nn_conv3x3_async(self.ctx, gy, gy.shape[3], gyoff, d["wt"], None, gx,
                                     gx.shape[3], gxoff, n, s, s, d["coi"], d["ci"], relu=0,
-                                    stream=self.stream)
+                                    stream=self.stream, **mask)
 
     def _mask(self, g, goff, a, aoff, c):
         n, s = g.shape[0], g.shape[1]
@@ -247,43 +252,35 @@ class UNet:
 
     def backward(self):
         A, G = self.A, self.G
-        self._layer_back("h_b", A["h_a"], 0, G["out"], 0, G["h_a"], 0)
-        self._mask(G["h_a"], 0, A["h_a"], 0, 16)
+        self._layer_back("h_b", A["h_a"], 0, G["out"], 0, G["h_a"], 0, relu_of=A["h_a"])
         self._layer_back("h_a", A["u0"], 0, G["h_a"], 0, G["u0"], 0)
         self._up(G["u0"], 0, G["d1b"], 0, 32, backward=True)
         self._mask(G["d1b"], 0, A["d1b"], 0, 32)
-        self._layer_back("d1b", A["d1a"], 0, G["d1b"], 0, G["d1a"], 0)
-        self._mask(G["d1a"], 0, A["d1a"], 0, 32)
+        self._layer_back("d1b", A["d1a"], 0, G["d1b"], 0, G["d1a"], 0, relu_of=A["d1a"])
         self._layer_back("d1a", A["cat1"], 0, G["d1a"], 0, G["cat1"], 0)
         self._up(G["cat1"], 0, G["d2b"], 0, 64, backward=True)
         self._mask(G["d2b"], 0, A["d2b"], 0, 64)
-        self._layer_back("d2b", A["d2a"], 0, G["d2b"], 0, G["d2a"], 0)
-        self._mask(G["d2a"], 0, A["d2a"], 0, 64)
+        self._layer_back("d2b", A["d2a"], 0, G["d2b"], 0, G["d2a"], 0, relu_of=A["d2a"])
         self._layer_back("d2a", A["cat2"], 0, G["d2a"], 0, G["cat2"], 0)
         self._up(G["cat2"], 0, G["d3b"], 0, 128, backward=True)
         self._mask(G["d3b"], 0, A["d3b"], 0, 128)
-        self._layer_back("d3b", A["d3a"], 0, G["d3b"], 0, G["d3a"], 0)
-        self._mask(G["d3a"], 0, A["d3a"], 0, 128)
+        self._layer_back("d3b", A["d3a"], 0, G["d3b"], 0, G["d3a"], 0, relu_of=A["d3a"])
         self._layer_back("d3a", A["cat3"], 0, G["d3a"], 0, G["cat3"], 0)
         self._up(G["cat3"], 0, G["b_b"], 0, 256, backward=True)
         self._mask(G["b_b"], 0, A["b_b"], 0, 256)
-        self._layer_back("b_b", A["b_a"], 0, G["b_b"], 0, G["b_a"], 0)
-        self._mask(G["b_a"], 0, A["b_a"], 0, 256)
+        self._layer_back("b_b", A["b_a"], 0, G["b_b"], 0, G["b_a"], 0, relu_of=A["b_a"])
         self._layer_back("b_a", A["p3"], 0, G["b_a"], 0, G["p3"], 0)
         self._pool(G["p3"], 0, G["cat3"], 256, 128, backward=True, acc=True)
         self._mask(G["cat3"], 256, A["cat3"], 256, 128)
-        self._layer_back("e3b", A["e3a"], 0, G["cat3"], 256, G["e3a"], 0)
-        self._mask(G["e3a"], 0, A["e3a"], 0, 128)
+        self._layer_back("e3b", A["e3a"], 0, G["cat3"], 256, G["e3a"], 0, relu_of=A["e3a"])
         self._layer_back("e3a", A["p2"], 0, G["e3a"], 0, G["p2"], 0)
         self._pool(G["p2"], 0, G["cat2"], 128, 64, backward=True, acc=True)
         self._mask(G["cat2"], 128, A["cat2"], 128, 64)
-        self._layer_back("e2b", A["e2a"], 0, G["cat2"], 128, G["e2a"], 0)
-        self._mask(G["e2a"], 0, A["e2a"], 0, 64)
+        self._layer_back("e2b", A["e2a"], 0, G["cat2"], 128, G["e2a"], 0, relu_of=A["e2a"])
         self._layer_back("e2a", A["p1"], 0, G["e2a"], 0, G["p1"], 0)
         self._pool(G["p1"], 0, G["cat1"], 64, 32, backward=True, acc=True)
         self._mask(G["cat1"], 64, A["cat1"], 64, 32)
-        self._layer_back("e1b", A["e1a"], 0, G["cat1"], 64, G["e1a"], 0)
-        self._mask(G["e1a"], 0, A["e1a"], 0, 32)
+        self._layer_back("e1b", A["e1a"], 0, G["cat1"], 64, G["e1a"], 0, relu_of=A["e1a"])
         self._layer_back("e1a", A["x"], 0, G["e1a"], 0, None)
 
     def adam_step(self):

@@ -224,6 +224,27 @@ def test_resample_paths(env, c, ldx, xoff, ldy, yoff, h, w):
         assert np.array_equal(got[..., yoff + c:], y0[..., yoff + c:]), (op, bw)
 
 
+@pytest.mark.parametrize("c,ldg,goff,ldy,yoff", [(48, 48, 0, 64, 16), (12, 20, 4, 16, 2)])
+def test_relu_mask_paths(env, c, ldg, goff, ldy, yoff):
+    """ReLU derivative on a gradient slice: 8 channels per thread when aligned, else
+    element by element; zeros (and negatives) of the activation mask."""
+    torch, ctx = env
+    say("relu mask paths", c, ldg, goff, ldy, yoff)
+    rng = np.random.default_rng(c + ldy)
+    npix = 3 * 50
+    y = U.bf16_round(rng.normal(size=(npix, ldy)))
+    y[rng.random(size=y.shape) < 0.1] = 0.0
+    g0 = U.bf16_round(rng.normal(size=(npix, ldg)))
+    dg = torch.from_numpy(to_bf16_bits(g0)).cuda()
+    dy = torch.from_numpy(to_bf16_bits(y)).cuda()
+    mcx.mc_nn_relu_mask_async(ctx, dg, ldg, goff, dy, ldy, yoff, npix, c)
+    torch.cuda.synchronize()
+    got = from_bf16_bits(dg)
+    want = g0.copy()
+    want[:, goff:goff + c] = np.where(y[:, yoff:yoff + c] > 0, g0[:, goff:goff + c], 0.0)
+    assert np.array_equal(got, want)
+
+
 def small_net(torch, ctx, n=2, s=32, seed=3):
     p = U.init_params(seed)
     rng = np.random.default_rng(seed)
