@@ -117,6 +117,42 @@ def test_pd_full_size_subrange(gpu):
     g.close()
 
 
+def test_pd_bench_configuration_subrange(gpu):
+    """The benchmark's point-detector configuration (512^3 object, 2048^2 panel,
+    mixed estimator, split 20, 1 keV roulette) in the launch shape bench.py
+    times: a photon sub-range against the oracle's image of the same photons,
+    with equal scored, killed and chord-step counts."""
+    torch = gpu
+    w = inputs.workload("ellipsoids512_hires")
+    o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"])
+    g.set_launch(256, 0, 58)
+    for side, mode in zip((o, g), MODES[1]):
+        side.set_estimator(mode, 20, 1.0)
+    geo = w["geometry"]
+    a, m = 500_000_321, 5_000
+    say("512^3 point detector (bench configuration) sub-range", a, m)
+    p = torch.zeros((geo["nv"], geo["nu"]), dtype=torch.int64, device="cuda:0")
+    s = torch.zeros((geo["snv"], geo["snu"]), dtype=torch.int64, device="cuda:0")
+    g.stats(True)
+    mcx.mc_project_range_async(g.ctx, w["angle"], a, m, w["seed"], p, s)
+    torch.cuda.synchronize()
+    st_g = g.stats()
+    g.stats(False)
+    o.stats()
+    po, so = o.project_range(w["angle"], a, m, w["seed"])
+    st_o = o.stats()
+    sg = s.cpu().numpy()
+    r = rel_l2(sg, so)
+    say("512^3 sub-range scatter rel-L2", r, "differing bins", int((sg != so).sum()),
+        "scores", st_g["pd_scores"], "killed", st_g["pd_killed"])
+    assert np.array_equal(p.cpu().numpy(), po)
+    assert so.sum() > 0 and r <= PD_REL
+    for k in ("pd_scores", "pd_killed", "pd_steps"):
+        assert st_g[k] == st_o[k], k
+    assert st_g["pd_killed"] > 0
+    g.close()
+
+
 def test_pd_launch_shapes_and_ranges(gpu):
     torch = gpu
     w = inputs.workload("cylinder64")
