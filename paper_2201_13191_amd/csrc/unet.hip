@@ -426,14 +426,14 @@ __global__ void __launch_bounds__(256) conv3x3_lds_kernel(const ConvArgs a) {
     conv_epilogue<WM, WN>(a, acc, px0, co0, npix, (float *)(lds + wave * kLdsInElems), lane);
 }
 
-// The same staging for layers with few tiles, whose reduction is split over
-// KS waves of a block (16-channel chunks c = ks, ks + KS, ...; partial tiles
-// added in LDS in a fixed order).  Each wave stages its chunk's input window
-// in its own LDS rows, with the weights read through L1/L2.  The window is
-// the tile's image rows and one more on each side: for widths that are
-// multiples of 64 one row of 66 pixels, for widths of 16 or 32 (a 64-pixel
-// tile is 4 or 2 whole rows) the rows at their full width plus the zero
-// columns at both ends.
+// The same staging for layers with few tiles, whose reduction is split over KS
+// waves of a block (16-channel chunks c = ks, ks + KS, ...; partial tiles added
+// in LDS in a fixed order).  Each wave stages its chunk's input window in its
+// own LDS rows; the chunk's weights (nine taps) are loaded into registers
+// through L1/L2 at once.  The window is the tile's image rows and one more on
+// each side: for widths that are multiples of 64 one row of 66 pixels, for
+// widths of 16 or 32 (a 64-pixel tile is 4 or 2 whole rows) the rows at their
+// full width plus the zero columns at both ends.
 template <int WN, int KS>
 __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a) {
     constexpr int WM = 2, TPB = 4 / KS;
@@ -489,6 +489,15 @@ __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a
     if (live && ks < kc) {
         load_chunk(ks);
         for (int c = ks; c < kc; c += KS) {
+            // the chunk's nine taps of weights, all in flight at once (one wait
+            // per chunk rather than one per tap)
+            bf16x8 bw[9][WN];
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    bw[tap][j] = *(const bf16x8 *)(a.w + (size_t)(co0 + j * 32 + lr) * wk +
+                                                   (size_t)tap * a.cin + c * 16 + kh * 8);
 #pragma unroll
             for (int m = 0; m < kInPer; ++m) {
                 const int t = lane + 64 * m;
@@ -500,21 +509,16 @@ __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a
             for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const int tap = 3 * r + k;
-                    bf16x8 av[WM], bv[WN];
+                    bf16x8 av[WM];
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
                         av[i] = *(const bf16x8 *)(in + (aoff[i] + r * wn + k) * 16 + kh * 8);
-#pragma unroll
-                    for (int j = 0; j < WN; ++j)
-                        bv[j] = *(const bf16x8 *)(a.w + (size_t)(co0 + j * 32 + lr) * wk +
-                                                  (size_t)tap * a.cin + c * 16 + kh * 8);
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
 #pragma unroll
                         for (int j = 0; j < WN; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                av[i], bv[j], acc[i][j], 0, 0, 0);
+                                av[i], bw[3 * r + k][j], acc[i][j], 0, 0, 0);
                 }
             wave_sync();      // the next chunk overwrites the rows
         }
