@@ -441,10 +441,14 @@ def main():
         g.set_launch(0, 0, 0)
         # the probe gathers every step; compare the transport's executed lookups
         t_rate = (st["steps"] - st.get("skipped_steps", 0)) / launch_s
+        # and, beside it, the march steps the transport advances its photons by
+        # (uniform runs included) against the probe's
+        s_rate = st["steps"] / launch_s
         probe = {"steps_per_s": best[0], "refill_batch": best[1],
                  "blocks_per_cu": best[2] or "occupancy", "rays": n_rays,
                  "gather_GBs": best[0] * gather_bytes / 1e9,
-                 "transport_lookups_per_s": t_rate, "frac": t_rate / best[0]}
+                 "transport_lookups_per_s": t_rate, "frac": t_rate / best[0],
+                 "transport_steps_per_s": s_rate, "steps_frac": s_rate / best[0]}
         log(f"march probe {best[0]:.4g} steps/s (refill {best[1]}), transport "
             f"{t_rate:.4g} voxel lookups/s = {t_rate / best[0]:.1%}")
 
