@@ -35,3 +35,26 @@ def test_network_gain_small_training(tmp_path):
     # of the same input): measured 6.8 % against 11.6 % at this size
     assert r["unet"]["debiased_mean"] < r["sg_cubic"]["debiased_mean"]
     assert out["plain_mc"]["histories_per_s"] > 1e8
+
+
+def test_point_detector_inputs_pipeline(tmp_path):
+    """The same pipeline with point-detector inputs (single projections spread
+    over concurrent streams): it runs end to end and the network still beats
+    the up-sampled input it is given."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on the MI355X box")
+    from paper_2201_13191_amd import learned
+    say("learned pipeline, point-detector inputs, 96 pairs")
+    out = learned.main(["--phantoms", "24", "--angles", "4", "--test-phantoms", "2",
+                        "--test-angles", "2", "--n-in", "1000000", "--n-tgt", "20000000",
+                        "--n-ref", "200000000", "--ref-batches", "4", "--epochs", "2",
+                        "--batch", "8", "--pd-split", "8", "--pd-rr", "1.0",
+                        "--out", str(tmp_path / "l.json")])
+    r = out["rel_rms"]
+    say("debiased rel-RMS raw", r["raw_cubic"]["debiased_mean"], "unet",
+        r["unet"]["debiased_mean"], "MC per projection", out["learned"]["mc_seconds"])
+    assert out["pairs"] == 96 and out["pd_split"] == 8
+    assert all(math.isfinite(v) for v in out["losses"])
+    assert r["unet"]["debiased_mean"] < r["raw_cubic"]["debiased_mean"]
+    assert 0 < out["learned"]["mc_seconds"] < 1.0
