@@ -324,6 +324,10 @@ constexpr size_t conv_lds_bytes() { return (4 * kLdsInElems + lds_w_elems<WN>())
 #define MCX_CONV_LDS 1
 #endif
 constexpr bool conv_lds_enabled = MCX_CONV_LDS != 0;
+#ifndef MCX_CONV_HALF_TILES
+#define MCX_CONV_HALF_TILES 1
+#endif
+constexpr bool conv_half_tiles = MCX_CONV_HALF_TILES != 0;
 
 template <int WN>
 __global__ void __launch_bounds__(256) conv3x3_lds_kernel(const ConvArgs a) {
@@ -434,11 +438,13 @@ __global__ void __launch_bounds__(256) conv3x3_lds_kernel(const ConvArgs a) {
 // each side: for widths that are multiples of 64 one row of 66 pixels, for
 // widths of 16 or 32 (a 64-pixel tile is 4 or 2 whole rows) the rows at their
 // full width plus the zero columns at both ends.
-template <int WN, int KS>
+template <int WM, int WN, int KS>
 __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a) {
-    constexpr int WM = 2, TPB = 4 / KS;
+    constexpr int TPB = 4 / KS;
+    constexpr int TPX = 32 * WM;                      // pixels per tile
     constexpr int R = WM * WN * 16;                   // floats per lane of a partial tile
-    constexpr int kInPer = (3 * kLdsInPx * 2 + 63) / 64;
+    constexpr int kInPer = (3 * (TPX + 2) * 2 + 63) / 64;
+    static_assert(3 * (TPX + 2) <= 3 * kLdsInPx, "a window fits a wave's rows");
     static_assert(32 * kEpStride <= R * 64, "epilogue staging fits a partial tile");
     extern __shared__ __align__(16) float s_dyn[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -449,9 +455,9 @@ __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a
     const int px0 = (blockIdx.x * TPB + tile) * (32 * WM);
     const int co0 = blockIdx.y * (32 * WN);
     const bool live = px0 < npix;       // no early return: the block meets at barriers
-    const bool wide = a.w_ >= 64;
-    const int nr = wide ? 1 : 64 / a.w_;              // image rows of the tile
-    const int wn = wide ? kLdsInPx : a.w_ + 2;        // staged pixels per row
+    const bool wide = a.w_ >= TPX;
+    const int nr = wide ? 1 : TPX / a.w_;             // image rows of the tile
+    const int wn = wide ? TPX + 2 : a.w_ + 2;         // staged pixels per row
     const int row0 = live ? px0 / a.w_ : 0;           // n * h + y of the tile's first row
     const int xs = px0 - row0 * a.w_;                 // its first column (0 for whole rows)
     const int yy0 = row0 % a.h;
@@ -552,10 +558,10 @@ __global__ void __launch_bounds__(256) conv3x3_lds_split_kernel(const ConvArgs a
     conv_epilogue<WM, WN>(a, acc, px0, co0, npix, (float *)base, lane);
 }
 
-template <int WN, int KS>
+template <int WM, int WN, int KS>
 constexpr size_t conv_lds_split_bytes() {
     constexpr size_t rows = 4 * kLdsInElems * 2;
-    constexpr size_t parts = (size_t)(4 / KS) * (KS - 1) * 2 * WN * 16 * 64 * sizeof(float);
+    constexpr size_t parts = (size_t)(4 / KS) * (KS - 1) * WM * WN * 16 * 64 * sizeof(float);
     return rows > parts ? rows : parts;
 }
 
@@ -1001,12 +1007,23 @@ static hipError_t conv_launch(const ConvArgs &a, int tiles_co, hipStream_t s) {
         // the reduction split over 2 or 4 waves by 16-channel chunks
         if (tiles >= 1024 || a.cin < 64) {
             const dim3 grid((tiles_px + 1) / 2, tiles_co);
-            hipLaunchKernelGGL((conv3x3_lds_split_kernel<WN, 2>), grid, dim3(256),
-                               (conv_lds_split_bytes<WN, 2>()), s, a);
+            hipLaunchKernelGGL((conv3x3_lds_split_kernel<2, WN, 2>), grid, dim3(256),
+                               (conv_lds_split_bytes<2, WN, 2>()), s, a);
         } else {
+            if constexpr (WN == 2) {
+                if (conv_half_tiles && tiles < 512 && a.cin <= 256) {
+                    // the fewest tiles with short reductions: 32-pixel tiles,
+                    // twice as many waves (with long reductions the weights,
+                    // loaded per tile, cost more than the waves gain)
+                    const dim3 grid(2 * tiles_px, tiles_co);
+                    hipLaunchKernelGGL((conv3x3_lds_split_kernel<1, WN, 4>), grid, dim3(256),
+                                       (conv_lds_split_bytes<1, WN, 4>()), s, a);
+                    return hipGetLastError();
+                }
+            }
             const dim3 grid(tiles_px, tiles_co);
-            hipLaunchKernelGGL((conv3x3_lds_split_kernel<WN, 4>), grid, dim3(256),
-                               (conv_lds_split_bytes<WN, 4>()), s, a);
+            hipLaunchKernelGGL((conv3x3_lds_split_kernel<2, WN, 4>), grid, dim3(256),
+                               (conv_lds_split_bytes<2, WN, 4>()), s, a);
         }
     } else if (tiles >= 1024 || K < 16) {
         const dim3 grid((tiles_px + 1) / 2, tiles_co);
