@@ -277,8 +277,7 @@ def main():
         g.set_layout({"lane": mcx.MC_LAYOUT_PALETTE_LANE, "shared": mcx.MC_LAYOUT_PALETTE_SHARED,
                       "generic": mcx.MC_LAYOUT_GENERIC}[args.layout])
     # set-up, outside the timed region and reported on its own: the object's
-    # upload (with its layout and uniform-cell map), the tables, and a first
-    # one-photon launch (lazy uploads, module load)
+    # upload (with its layout and uniform-cell map) and the geometry and tables
     t_s = time.perf_counter()
     g.load_phantom(w["ids"], w["rho"], w["voxel_mm"])
     t_p = time.perf_counter()
@@ -290,13 +289,9 @@ def main():
     prim = torch.empty((geo["nv"], geo["nu"]), dtype=torch.int64, device=dev)
     scat = torch.empty((geo["snv"], geo["snu"]), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
-    t_f = time.perf_counter()
-    mcx.mc_project_async(g.ctx, w["angle"], 1, w["seed"], prim, scat, stream)
-    torch.cuda.synchronize()
-    setup = {"load_phantom_s": t_p - t_s, "geometry_and_tables_s": t_t - t_p,
-             "first_launch_s": time.perf_counter() - t_f}
+    setup = {"load_phantom_s": t_p - t_s, "geometry_and_tables_s": t_t - t_p}
     log(f"set-up: phantom {setup['load_phantom_s']:.2f} s, geometry and tables "
-        f"{setup['geometry_and_tables_s']:.3f} s, first launch {setup['first_launch_s']:.3f} s")
+        f"{setup['geometry_and_tables_s']:.3f} s")
 
     def step():
         mcx.mc_project_async(g.ctx, w["angle"], n, w["seed"], prim, scat, stream)
