@@ -110,6 +110,7 @@ struct KParams {
     int event_batch;           // lanes that must wait before a wave handles events
     unsigned long long *prim, *scat;     // int64 tallies (two's complement adds)
     unsigned long long *counter;         // next photon index (relative to first)
+    uint32_t chunk;            // photon ids a wave reserves per counter update (>= 1)
     unsigned long long *stats;           // mc_stats layout, or null
     const int *cancel;                   // host-memory cancellation flag (mapped), or null
     // batch: jobs run in order, each wave moving to the next job when the

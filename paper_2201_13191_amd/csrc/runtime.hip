@@ -89,6 +89,10 @@ constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
 constexpr int kDefaultEventBatch = 58;        // single projections (swept 54..62)
+#ifndef MCX_MAX_CHUNK
+#define MCX_MAX_CHUNK 1024
+#endif
+constexpr uint64_t kMaxChunk = MCX_MAX_CHUNK;  // photon ids a wave reserves at most at once
 constexpr int kDefaultBatchEventBatch = 54;   // batched launches (swept 48..60)
 }  // namespace
 
@@ -499,6 +503,12 @@ mc_status run(mc_ctx *c, KParams &p, hipStream_t s, bool debug) {
     int grid, block;
     launch_shape(c, p, layout, stats, grid, block);
     if (!stats) p.stats = nullptr;
+    // each wave reserves this many photon ids per update of the launch's
+    // counter (one address all waves share): about an eighth of a wave's share,
+    // 64 .. 1024
+    const uint64_t waves = (uint64_t)grid * (uint64_t)(block / 64);
+    p.chunk = (uint32_t)std::min<uint64_t>(kMaxChunk,
+                                           std::max<uint64_t>(64, p.n / (8 * std::max<uint64_t>(waves, 1))));
     hipError_t e = launch_transport(p, layout, grid, block, stats, debug, s);
     if (e != hipSuccess) return hip_fail(c, e, "transport launch");
     return MC_OK;

@@ -597,6 +597,11 @@ transport_kernel(const KParams p) {
     };
 
     bool alive = false, flying = false, exhausted = false;
+    // single projections: the wave's reserved photon ids [res_next, res_end)
+    // (relative to first); a reservation takes p.chunk ids from the launch's
+    // counter, so the counter, which every wave updates, sees one atomic per
+    // chunk rather than one per refill
+    uint64_t res_next = 0, res_end = 0;
     uint32_t rounds = 0;     // scheduling rounds of this wave (cancellation checks)
     PhotonStream rng;
     uint64_t pid = 0;
@@ -995,45 +1000,79 @@ transport_kernel(const KParams p) {
             }
             alive = false;
         }
-        // ---- 3. refill dead lanes: one atomic per wave (per job touched)
+        // ---- 3. refill dead lanes: from the wave's reserved ids (single
+        //         projections) or with one atomic per wave per job touched (batches)
         // A cancellation request (a flag in host memory, read every 64th round
-        // of a wave) ends the launch's intake: the photons in flight finish.
+        // of a wave) ends the launch's intake: the photons in flight, and the
+        // ids a wave has reserved, finish.
         if (!exhausted && p.cancel != nullptr && (++rounds & 63u) == 0u) {
             int flag = 0;
             if (lane == 0)
                 flag = __hip_atomic_load(p.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             if (__builtin_amdgcn_readfirstlane(flag) != 0) exhausted = true;
         }
-        if (!exhausted) {
+        if (!BATCH) {
+            // dead lanes take the reserved ids in lane order, then a new chunk's
+            // when the reservation runs short.  Reserved ids are always used up
+            // (also after a cancellation, which only stops new reservations),
+            // so the photons a launch runs are the prefix [0, counter).
+            const unsigned long long dead = __ballot(!alive);
+            const unsigned nd = (unsigned)__popcll(dead);
+            const uint64_t avail = res_end - res_next;
+            uint64_t cb = 0, ce = 0;
+            if (nd > 0 && avail < nd && !exhausted) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(p.counter, (unsigned long long)p.chunk);
+                base = lane_value(base, 0);
+                if (base >= p.n) {
+                    exhausted = true;
+                } else {
+                    cb = base;
+                    ce = p.n - base < p.chunk ? p.n : base + p.chunk;
+                }
+            }
+            if (!alive) {
+                const uint64_t rank = (uint64_t)__popcll(dead & ((1ull << lane) - 1ull));
+                if (rank < avail)
+                    birth(p.first + res_next + rank, p.key0, p.key1, p.F);
+                else if (rank - avail < ce - cb)
+                    birth(p.first + cb + (rank - avail), p.key0, p.key1, p.F);
+            }
+            if (avail >= nd) {
+                res_next += nd;
+            } else if (ce > cb) {
+                const uint64_t used = (uint64_t)nd - avail;
+                res_next = used < ce - cb ? cb + used : ce;
+                res_end = ce;
+            } else {
+                res_next = res_end;
+            }
+        } else if (!exhausted) {
+            // batches: one atomic per wave on the current job's counter for all
+            // its dead lanes, moving to the next job when this one runs out
             unsigned long long dead = __ballot(!alive);
             while (dead) {
                 const unsigned nd = (unsigned)__popcll(dead);
                 const int leader = __ffsll(dead) - 1;
                 const int cj = __builtin_amdgcn_readfirstlane(cur_job);
-                const JobDesc cd = BATCH ? job_desc(cj) : JobDesc{};
-                unsigned long long *ctr = BATCH ? p.job_counters + cj : p.counter;
-                const unsigned long long total = BATCH ? cd.n : p.n;
+                const JobDesc cd = job_desc(cj);
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(ctr, (unsigned long long)nd);
+                if (lane == leader) base = atomicAdd(p.job_counters + cj, (unsigned long long)nd);
                 base = lane_value(base, leader);
                 const unsigned long long got =
-                    base < total ? (total - base < nd ? total - base : nd) : 0ull;
+                    base < cd.n ? (cd.n - base < nd ? cd.n - base : nd) : 0ull;
                 if (!alive) {
                     const unsigned long long rank =
                         (unsigned long long)__popcll(dead & ((1ull << lane) - 1ull));
                     if (rank < got) {
-                        if (BATCH) {
-                            job = cj;
-                            gi = cd.grid;
-                            birth(base + rank, cd.key0, cd.key1, cd.F);
-                        } else {
-                            birth(p.first + base + rank, p.key0, p.key1, p.F);
-                        }
+                        job = cj;
+                        gi = cd.grid;
+                        birth(base + rank, cd.key0, cd.key1, cd.F);
                     }
                 }
-                if (got == nd && base + nd < total) break;
+                if (got == nd && base + nd < cd.n) break;
                 // the current job has no photons left
-                if (BATCH && cur_job + 1 < p.n_jobs) {
+                if (cur_job + 1 < p.n_jobs) {
                     ++cur_job;
                     dead = __ballot(!alive);
                 } else {
