@@ -267,7 +267,8 @@ mc_status mc_to_density_async(mc_ctx *ctx, const float *d_mu, uint64_t n, float 
 /* Cancellation, for callers that must stop a long projection or batch: with
  * on = 1 every transport launch of the context that is running or queued stops
  * taking photons (each wave reads the flag, kept in mapped host memory, every
- * 64th scheduling round) and ends once the photons it holds are finished:
+ * 64th scheduling round) and ends once the photons it holds, and the photon
+ * ids its waves have reserved (at most 1024 per wave), are finished:
  * each projection's images then hold photons 0 .. m-1 for some m, bitwise what
  * a run of m photons gives, and nothing faults or hangs.  Launches made while
  * the flag is on stop within their first rounds.

@@ -485,6 +485,13 @@ mc_status prepare(mc_ctx *c, float beta, uint64_t first, uint64_t n, uint64_t se
     return MC_OK;
 }
 
+// photon ids a wave reserves per update of a counter that every wave of the
+// launch updates: about an eighth of a wave's share of n, 64 .. kMaxChunk
+uint32_t reservation_chunk(uint64_t n, int grid, int block) {
+    const uint64_t waves = std::max<uint64_t>(1, (uint64_t)grid * (uint64_t)(block / 64));
+    return (uint32_t)std::min<uint64_t>(kMaxChunk, std::max<uint64_t>(64, n / (8 * waves)));
+}
+
 void launch_shape(mc_ctx *c, const KParams &p, int layout, bool stats, int &grid, int &block) {
     block = c->block > 0 ? c->block : 256;
     const int bpc = c->blocks_per_cu > 0 ? c->blocks_per_cu
@@ -503,12 +510,7 @@ mc_status run(mc_ctx *c, KParams &p, hipStream_t s, bool debug) {
     int grid, block;
     launch_shape(c, p, layout, stats, grid, block);
     if (!stats) p.stats = nullptr;
-    // each wave reserves this many photon ids per update of the launch's
-    // counter (one address all waves share): about an eighth of a wave's share,
-    // 64 .. 1024
-    const uint64_t waves = (uint64_t)grid * (uint64_t)(block / 64);
-    p.chunk = (uint32_t)std::min<uint64_t>(kMaxChunk,
-                                           std::max<uint64_t>(64, p.n / (8 * std::max<uint64_t>(waves, 1))));
+    p.chunk = reservation_chunk(p.n, grid, block);
     hipError_t e = launch_transport(p, layout, grid, block, stats, debug, s);
     if (e != hipSuccess) return hip_fail(c, e, "transport launch");
     return MC_OK;
@@ -893,6 +895,7 @@ void batch_params(mc_ctx *c, const BatchPlan &b, unsigned char *db, int n_jobs, 
                                      : batch_blocks_per_cu(p, b.max_lane_pal, block, stats);
     grid = (int)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)bpc * c->n_cu, (b.total + block - 1) / block));
+    p.chunk = reservation_chunk(b.total, grid, block);
 }
 
 }  // namespace

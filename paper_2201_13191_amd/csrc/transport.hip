@@ -597,11 +597,12 @@ transport_kernel(const KParams p) {
     };
 
     bool alive = false, flying = false, exhausted = false;
-    // single projections: the wave's reserved photon ids [res_next, res_end)
-    // (relative to first); a reservation takes p.chunk ids from the launch's
-    // counter, so the counter, which every wave updates, sees one atomic per
-    // chunk rather than one per refill
+    // the wave's reserved photon ids [res_next, res_end) (single projections:
+    // relative to first; batches: of job res_job); a reservation takes p.chunk
+    // ids from the launch's (or the job's) counter, so the counter, which every
+    // wave updates, sees one atomic per chunk rather than one per refill
     uint64_t res_next = 0, res_end = 0;
+    int res_job = 0;      // batch: the job of the reserved ids
     uint32_t rounds = 0;     // scheduling rounds of this wave (cancellation checks)
     PhotonStream rng;
     uint64_t pid = 0;
@@ -1000,8 +1001,7 @@ transport_kernel(const KParams p) {
             }
             alive = false;
         }
-        // ---- 3. refill dead lanes: from the wave's reserved ids (single
-        //         projections) or with one atomic per wave per job touched (batches)
+        // ---- 3. refill dead lanes from the wave's reserved photon ids
         // A cancellation request (a flag in host memory, read every 64th round
         // of a wave) ends the launch's intake: the photons in flight, and the
         // ids a wave has reserved, finish.
@@ -1047,37 +1047,42 @@ transport_kernel(const KParams p) {
             } else {
                 res_next = res_end;
             }
-        } else if (!exhausted) {
-            // batches: one atomic per wave on the current job's counter for all
-            // its dead lanes, moving to the next job when this one runs out
+        } else {
+            // batches: the reservation belongs to job res_job; a new one takes
+            // p.chunk ids of the current job, moving to the next job when this
+            // one has none left
             unsigned long long dead = __ballot(!alive);
             while (dead) {
-                const unsigned nd = (unsigned)__popcll(dead);
-                const int leader = __ffsll(dead) - 1;
+                const uint64_t avail = res_end - res_next;
+                if (avail > 0) {
+                    const JobDesc rd = job_desc(__builtin_amdgcn_readfirstlane(res_job));
+                    const unsigned nd = (unsigned)__popcll(dead);
+                    if (!alive) {
+                        const uint64_t rank = (uint64_t)__popcll(dead & ((1ull << lane) - 1ull));
+                        if (rank < avail) {
+                            job = res_job;
+                            gi = rd.grid;
+                            birth(res_next + rank, rd.key0, rd.key1, rd.F);
+                        }
+                    }
+                    res_next += avail < nd ? avail : nd;
+                    dead = __ballot(!alive);
+                    continue;
+                }
+                if (exhausted) break;
                 const int cj = __builtin_amdgcn_readfirstlane(cur_job);
                 const JobDesc cd = job_desc(cj);
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(p.job_counters + cj, (unsigned long long)nd);
-                base = lane_value(base, leader);
-                const unsigned long long got =
-                    base < cd.n ? (cd.n - base < nd ? cd.n - base : nd) : 0ull;
-                if (!alive) {
-                    const unsigned long long rank =
-                        (unsigned long long)__popcll(dead & ((1ull << lane) - 1ull));
-                    if (rank < got) {
-                        job = cj;
-                        gi = cd.grid;
-                        birth(base + rank, cd.key0, cd.key1, cd.F);
-                    }
-                }
-                if (got == nd && base + nd < cd.n) break;
-                // the current job has no photons left
-                if (cur_job + 1 < p.n_jobs) {
-                    ++cur_job;
-                    dead = __ballot(!alive);
+                if (lane == 0) base = atomicAdd(p.job_counters + cj, (unsigned long long)p.chunk);
+                base = lane_value(base, 0);
+                if (base < cd.n) {
+                    res_job = cj;
+                    res_next = base;
+                    res_end = cd.n - base < p.chunk ? cd.n : base + p.chunk;
+                } else if (cur_job + 1 < p.n_jobs) {
+                    ++cur_job;          // the current job has no photons left
                 } else {
                     exhausted = true;
-                    break;
                 }
             }
         }
