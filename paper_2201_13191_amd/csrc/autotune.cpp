@@ -143,7 +143,7 @@ mc_status mc_autotune(mc_ctx *ctx, float angle_rad, uint64_t n_photons, uint64_t
     for (int table : tables)
         for (int block : {64, 128, 256})
             for (int bpc : {0, 2})
-                for (int batch : {48, 52, 56, 58, 60}) cands.push_back({block, bpc, batch, table});
+                for (int batch : {36, 40, 44, 48, 52, 58}) cands.push_back({block, bpc, batch, table});
     std::vector<int64_t> h_ref(np + ns), h_cur(np + ns);
     Shape best{0, 0, 0, layout};
     float best_ms = 1e30f;
@@ -262,7 +262,7 @@ mc_status mc_autotune_batch(mc_ctx *ctx, const mc_job *jobs, int n_jobs, int64_t
     for (int table : {MC_LAYOUT_PALETTE_LANE, MC_LAYOUT_PALETTE_SHARED})
         for (int block : {128, 256})
             for (int bpc : {0, 1, 2})
-                for (int batch : {48, 54, 60}) cands.push_back({block, bpc, batch, table});
+                for (int batch : {40, 48, 54}) cands.push_back({block, bpc, batch, table});
     hipStream_t stream = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess ||

@@ -88,12 +88,12 @@ namespace {
 constexpr int kRing = 64;
 constexpr int kCtlWords = kRing + 16;
 constexpr int kMaxLanePalette = 32;   // palettes up to this size get per-lane mu tables
-constexpr int kDefaultEventBatch = 58;        // single projections (swept 54..62)
+constexpr int kDefaultEventBatch = 44;        // single projections (swept 8..62)
 #ifndef MCX_MAX_CHUNK
 #define MCX_MAX_CHUNK 1024
 #endif
 constexpr uint64_t kMaxChunk = MCX_MAX_CHUNK;  // photon ids a wave reserves at most at once
-constexpr int kDefaultBatchEventBatch = 54;   // batched launches (swept 48..60)
+constexpr int kDefaultBatchEventBatch = 48;   // batched launches (swept 32..60)
 }  // namespace
 
 // One voxel object on the device: bricked one-byte codes (palette index, or

@@ -30,8 +30,8 @@ def test_autotune_and_cache(tmp_path):
     t = mcx.mc_autotune(g.ctx, 0.2, 200_000, 5, cache)
     say("autotune result", t)
     # 3 block sizes x 2 blocks per CU x 5 event batches x 2 table layouts
-    assert t["from_cache"] == 0 and t["candidates"] == 60 and t["rejected"] == 0
-    assert t["block"] in (64, 128, 256) and 48 <= t["event_batch"] <= 60
+    assert t["from_cache"] == 0 and t["candidates"] == 72 and t["rejected"] == 0
+    assert t["block"] in (64, 128, 256) and 36 <= t["event_batch"] <= 58
     assert t["table_layout"] in (mcx.MC_LAYOUT_PALETTE_LANE, mcx.MC_LAYOUT_PALETTE_SHARED)
     p, s = g.project(0.2, 200_000, 5)          # runs with the tuned shape
     assert np.array_equal(p, ref[0]) and np.array_equal(s, ref[1])
