@@ -383,8 +383,18 @@ def main():
         n_pd = max(1, int(n * args.pd_fraction))
         g.set_estimator(mcx.MC_SCORE_POINT_MIXED if args.pd_mixed else mcx.MC_SCORE_POINT,
                         args.pd_split, args.pd_rr)
+        pd_tuning = None
         if args.pd_launch:
             g.set_launch(*[int(v) for v in args.pd_launch.split(",")])
+        elif tuning is not None:
+            # the analog shape came from the autotuner: tune the point-detector
+            # kernel too (its own candidates, checked bitwise; not cached, the
+            # cache key does not tell the estimators apart)
+            log("autotune (point detector)")
+            pd_tuning = mcx.mc_autotune(g.ctx, w["angle"], n_pd, w["seed"] + 9, None)
+            log(f"autotune (point detector): block {pd_tuning['block']}, blocks/CU "
+                f"{pd_tuning['blocks_per_cu']}, event batch {pd_tuning['event_batch']}, "
+                f"table layout {pd_tuning['table_layout']}")
         mcx.mc_project_async(g.ctx, w["angle"], n_pd, w["seed"], prim, scat, stream)
         torch.cuda.synchronize()
         imgs, times = [], []
@@ -397,13 +407,19 @@ def main():
             times.append(a.elapsed_time(b) * 1e-3)
             imgs.append(scat.cpu().numpy())
         g.set_estimator(mcx.MC_SCORE_ANALOG)
-        if args.pd_launch:
+        if args.pd_launch or pd_tuning:
             g.set_launch(*launch_shape)
+            if tuning is not None:
+                tl = tuning["table_layout"]
+                g.set_layout(mcx.MC_LAYOUT_AUTO if tl == mcx.MC_LAYOUT_PALETTE_LANE else tl)
         t_pd = float(np.mean(times))
         r_pd = metrics.pair_rel_rms(*imgs)
         n2_pd = n_pd * (r_pd / 0.02) ** 2
         pd = {"estimator": "mixed" if args.pd_mixed else "point", "split": args.pd_split,
               "roulette_kev": args.pd_rr, "photons": n_pd,
+              "launch": ({k: pd_tuning[k] for k in ("block", "blocks_per_cu", "event_batch",
+                                                     "table_layout")} if pd_tuning else
+                         args.pd_launch or "as the analog step"),
               "ms_per_projection": t_pd * 1e3, "histories_per_s": n_pd / t_pd,
               "scatter_rel_rms": r_pd, "photons_for_2pct": n2_pd,
               "seconds_for_2pct": n2_pd * t_pd / n_pd,
