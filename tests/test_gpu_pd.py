@@ -121,7 +121,9 @@ def test_pd_bench_configuration_subrange(gpu):
     """The benchmark's point-detector configuration (512^3 object, 2048^2 panel,
     mixed estimator, split 20, 1 keV roulette) in the launch shape bench.py
     times: a photon sub-range against the oracle's image of the same photons,
-    with equal scored, killed and chord-step counts."""
+    with equal scored, killed and chord-step counts; then the same sub-range on
+    the shape the autotuner picks for this leg (shared palette table, two
+    blocks per CU), bitwise equal to the first."""
     torch = gpu
     w = inputs.workload("ellipsoids512_hires")
     o, g = pair(w["ids"], w["rho"], w["voxel_mm"], w["geometry"], w["spectrum"])
@@ -150,6 +152,14 @@ def test_pd_bench_configuration_subrange(gpu):
     for k in ("pd_scores", "pd_killed", "pd_steps"):
         assert st_g[k] == st_o[k], k
     assert st_g["pd_killed"] > 0
+    g.set_layout(mcx.MC_LAYOUT_PALETTE_SHARED)
+    g.set_launch(256, 2, 44)
+    say("512^3 point detector sub-range, shared palette, 2 blocks per CU")
+    p2, s2 = torch.zeros_like(p), torch.zeros_like(s)
+    mcx.mc_project_range_async(g.ctx, w["angle"], a, m, w["seed"], p2, s2)
+    torch.cuda.synchronize()
+    assert g.layout()[0] == mcx.MC_LAYOUT_PALETTE_SHARED
+    assert torch.equal(p2, p) and torch.equal(s2, s)
     g.close()
 
 
